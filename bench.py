@@ -1,0 +1,168 @@
+"""Benchmark: cell-ordinate sweep updates/s of ROM source iteration on one MI355X.
+
+One step = one pass of the whole hot path over the workload's synthetic input: ordinate
+ingestion (rom_set_ordinates), source iteration to convergence (sweeps + partial-flux combine +
+FP64 residual, replayed from a captured HIP graph) and the result left resident in HBM.  The
+default workload is c2 (256 x 256 checkerboard, 256 stratified random ordinates, FP32 sweeps,
+tolerance 1e-6).  Prints one JSON line.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload c2|c3|c4|c1] [--no-cpu]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+import rom_inputs as RI  # noqa: E402
+
+# Algorithmic work of one upwind cell-ordinate update: w*S (1 mul), + a*x and + b*y (2 fma = 4
+# flops), sigma_t + a + b (1 add), the division (1), and the scalar-flux accumulation (1 add).
+FLOPS_PER_UPDATE = 8
+FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X datasheet, FP32 vector
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+BF16_MFMA_PEAK_TFLOPS = 2500.0
+
+DESCR = {
+    "c1": "c1: 64x64, 32 iid sphere ordinates, sigma_t 1, sigma_s 0.5 iso, FP64, tol 1e-8",
+    "c2": "c2: 256x256 7x7 checkerboard, 256 stratified random ordinates (seed 0), FP32 sweeps, tol 1e-6",
+    "c3": "c3: 512x512, ensemble of 64 samples x 128 stratified random ordinates, FP32, tol 1e-6",
+    "c4": "c4: 256x256, HG g=0.8, 1024 stratified random ordinates, FP32 sweeps + BF16 MFMA contraction, tol 1e-6",
+}
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="c2", choices=sorted(DESCR))
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(workload, seconds):
+    """The FP64 oracle as it stands, on this host's cores, over whole solves of the same workload
+    (repeated until about `seconds` of work); result in updates/s."""
+    import oracle as O
+    wl = RI.WORKLOADS[workload]()
+    f = wl.fields[0]
+    prob = O.Problem(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    n = wl.n_ord[0]
+    if wl.ord_kind == "stratified":
+        nz, nt = O.stratified_spec(n)
+        dirs, w = O.generate(O.ORD_STRATIFIED, nz, nt, seed=wl.seed)
+    else:
+        dirs, w = O.generate(O.ORD_IID_SPHERE, n, seed=wl.seed)
+    W = None
+    if wl.scattering == "hg":
+        W = O.build_W(dirs, w, O.SCAT_HG, wl.g, fold=1)
+    updates, reps = 0, 0
+    t0 = time.perf_counter()
+    while True:
+        max_iter = wl.max_iter if W is None else 2  # anisotropic: a bounded sample of iterations
+        r = O.source_iterate(prob, dirs, w, W, tol=wl.tol if W is None else -1.0, max_iter=max_iter)
+        updates += r["iters"] * f.cells * n
+        reps += 1
+        if time.perf_counter() - t0 >= seconds:
+            break
+    dt = time.perf_counter() - t0
+    what = f"{reps} full solve(s) of {workload}" if W is None else f"{reps} x 2 SI iterations of {workload}"
+    return {"value": updates / dt, "unit": "updates/s", "cores": O.num_threads(), "kind": "oracle",
+            "sample": f"{what}, {updates:.3g} updates in {dt:.1f} s"}
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    from paper_2407_12527_amd import rom as R
+    torch.cuda.set_device(0)
+
+    wl = RI.WORKLOADS[a.workload]()
+    f = wl.fields[0]
+    h = R.Handle(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    n = wl.n_ord[0]
+    fp64 = wl.precision == "fp64"
+    prec = R.ROM_PREC_FP64 if fp64 else R.ROM_PREC_FP32
+    opts = R.si_opts(tol=wl.tol, max_iter=wl.max_iter, precision=prec, timing=1)
+    if wl.ord_kind == "stratified":
+        m = n // 4
+        nz = max(d for d in range(1, int(m ** 0.5) + 1) if m % d == 0)
+        spec = (R.ROM_ORD_STRATIFIED, nz, m // nz)
+    else:
+        spec = (R.ROM_ORD_IID_SPHERE, n, 0)
+    if wl.scattering == "hg":
+        h.set_scattering(R.ROM_SCAT_HG, wl.g)
+
+    ens = wl.samples > 1
+    dirs, w = R.generate_ordinates(spec[0], spec[1], spec[2], seed=wl.seed, sample=0)
+
+    def step():
+        if ens:
+            _, _, st, rc = h.ensemble(wl.samples, wl.seed, spec[0], spec[1], spec[2], opts, download=False)
+            return st.updates, 0.0, 0, st.max_iters
+        h.set_ordinates(dirs, w)                     # ordinate ingestion
+        _, st, rc = h.source_iterate(opts, download=False)
+        if rc != 0:
+            raise RuntimeError(f"solve did not converge (status {rc})")
+        return st.updates, st.sweep_ms, st.sweeps, st.iters
+
+    for _ in range(a.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    tot_upd, tot_sweep_ms, tot_sweeps, iters = 0, 0.0, 0, 0
+    for _ in range(a.steps):
+        u, sm, ns, it = step()
+        tot_upd += u
+        tot_sweep_ms += sm
+        tot_sweeps += ns
+        iters = it
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+
+    value = tot_upd / dt
+    roof = None
+    if tot_sweeps > 0:
+        avg_s = tot_sweep_ms / tot_sweeps / 1e3
+        upd_per_sweep = f.cells * n
+        achieved = FLOPS_PER_UPDATE * upd_per_sweep / avg_s / 1e12
+        peak = FP64_VECTOR_PEAK_TFLOPS if fp64 else FP32_VECTOR_PEAK_TFLOPS
+        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
+                "traffic": None, "kernel": "sweep_kernel", "avg_launch_us": avg_s * 1e6,
+                "updates_per_launch": upd_per_sweep}
+    out = {
+        "metric": "cell·ordinate sweep updates/s",
+        "value": value,
+        "unit": "updates/s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": dt / a.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if fp64 else "f32",
+        "data": "synthetic",
+        "config": {"workload": DESCR[a.workload], "cells": f.cells, "ordinates": n, "samples": wl.samples,
+                   "si_iterations": iters},
+        "roofline": roof,
+    }
+    if not a.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(a.workload, a.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

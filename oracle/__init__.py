@@ -31,7 +31,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(_LIB) and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC):
         return _LIB
     tmp = _LIB + ".tmp"
-    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-std=gnu11", "-fopenmp", "-ffp-contract=off", "-fno-builtin", "-fPIC", "-shared",
            "-Wall", "-o", tmp, _SRC, "-lm"]
     subprocess.check_call(cmd)
     os.replace(tmp, _LIB)

@@ -1,0 +1,1243 @@
+// rom_api.cpp -- host runtime of librom: the C ABI of include/rom.h, argument validation, the
+// solve plan (ordinate ingestion, lane packing, strip tickets, buffers), and the source-iteration,
+// ensemble and batch drivers that replay captured HIP graphs of the per-iteration kernels.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "rom_device.h"
+#include "rom_host.h"
+#include "rom_kernels.h"
+
+using namespace rom;
+
+namespace {
+
+// ------------------------------------------------------------------------------------ utilities
+thread_local std::string g_create_error;
+
+struct DevMem {
+    void* p = nullptr;
+    size_t bytes = 0;
+    DevMem() = default;
+    DevMem(const DevMem&) = delete;
+    DevMem& operator=(const DevMem&) = delete;
+    ~DevMem() { release(); }
+    void release()
+    {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        bytes = 0;
+    }
+    hipError_t alloc(size_t n)
+    {
+        release();
+        if (n == 0) n = 256;
+        hipError_t e = hipMalloc(&p, n);
+        if (e == hipSuccess) bytes = n;
+        else p = nullptr;
+        return e;
+    }
+    template <typename T>
+    T* as() const { return (T*)p; }
+};
+
+struct Fail {
+    int code;
+    std::string msg;
+};
+
+#define HIPCHK(expr)                                                                                       \
+    do {                                                                                                   \
+        hipError_t e_ = (expr);                                                                            \
+        if (e_ != hipSuccess)                                                                              \
+            throw Fail{e_ == hipErrorOutOfMemory ? ROM_E_NOMEM : ROM_E_DEVICE,                            \
+                       std::string(#expr) + ": " + hipGetErrorString(e_)};                                \
+    } while (0)
+
+inline bool isfin(double x) { return std::isfinite(x); }
+
+int quadrant_of(double c, double s)
+{
+    if (c >= 0.0 && s >= 0.0) return 0;
+    if (c < 0.0 && s >= 0.0) return 1;
+    if (c < 0.0 && s < 0.0) return 2;
+    return 3;
+}
+
+template <typename T>
+void upload(DevMem& d, const std::vector<T>& v)
+{
+    HIPCHK(d.alloc(v.size() * sizeof(T)));
+    if (!v.empty()) HIPCHK(hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
+}
+
+uint16_t f32_to_bf16(float f)
+{
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    if ((u & 0x7fffffffu) > 0x7f800000u) return 0x7fc0;  // NaN
+    u += 0x7fffu + ((u >> 16) & 1u);                      // round to nearest even
+    return uint16_t(u >> 16);
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------------------------ handle
+struct Plan;
+
+struct rom_handle {
+    rom_grid grid{};
+    double dx = 0, dy = 0;
+    int64_t cells = 0;
+    std::vector<double> st, ss, q;
+    std::vector<double> face[4];
+    // ordinates in the caller's order
+    int n = 0;
+    std::vector<double> dirs, w;
+    std::vector<double> ang[4];
+    // scattering
+    int scat = ROM_SCAT_ISO;
+    double g = 0.0;
+    std::vector<double> Pdense;
+    // execution
+    hipStream_t user_stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    int device = 0;
+    uint64_t version = 1;  // bumps whenever ordinates, inflow or scattering change
+    std::string err;
+    std::unique_ptr<Plan> plan;
+    uint64_t plan_version = 0;
+    std::string plan_sig;
+    // device-resident result of the last solve
+    const void* res_dev = nullptr;
+    bool res_fp64 = false;
+    DevMem ens_mean, ens_m2, ens_var;
+
+    hipStream_t stream()
+    {
+        if (user_stream) return user_stream;
+        if (!own_stream) HIPCHK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+        return own_stream;
+    }
+    ~rom_handle();
+};
+
+int fail(rom_handle* h, int code, const std::string& msg)
+{
+    if (h) h->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+// ------------------------------------------------------------------------------------ plan
+//
+// A plan packs a list of systems (problem + ordinate set) onto wave-streams and owns every
+// device buffer one solve needs.  Systems of one problem and quadrant share wave-streams; each
+// system's ordinates of a quadrant occupy whole groups of L lanes (padding lanes carry w = 0).
+struct SysInput {
+    rom_handle* h;
+    const double* dirs;
+    const double* w;
+    int n;
+    bool use_angular;  // angular inflow of the handle applies (its own ordinate set)
+};
+
+struct Plan {
+    bool fp64 = false, dd = false, aniso = false;
+    int tx = 16, ty = 16;
+    int esz = 4;
+    int nsys = 0, nws = 0, ntickets = 0, nslots = 0;
+    int grid = 1;
+    int max_iter = 0;
+    std::vector<rom_handle*> handles;  // one per problem
+    std::vector<ProblemDev> probs;
+    std::vector<SystemDev> sys;
+    std::vector<WaveStreamDev> ws;
+    std::vector<LaneDev> lanes;
+    std::vector<int2> tickets;
+    std::vector<int64_t> slot_off;
+    std::vector<int32_t> slot_order;
+    std::vector<int2> cblocks;
+    std::vector<std::vector<int>> user_of;  // per system: internal index -> caller index (-1 pad)
+    std::vector<int> sys_n;                 // per system: real ordinate count
+    std::vector<const double*> sys_w;       // per system: caller weights
+    std::vector<int> npad_al;               // per system: padded stride of the anisotropic layout
+    int cells_per_block = 4096;
+
+    DevMem d_probs, d_sys, d_ws, d_lanes, d_tickets, d_slot_off, d_slot_order, d_cblocks;
+    DevMem d_st, d_ss, d_q, d_src, d_phi, d_part, d_edge, d_inflow, d_prog, d_ctl, d_sysctl, d_rhist;
+    DevMem d_ang, d_psi, d_Pt;
+    std::vector<int64_t> pt_off;  // per system offset into d_Pt (elements)
+    hipGraphExec_t gexec = nullptr;
+    hipGraph_t graph = nullptr;
+    int graph_iters = 0;
+    int graph_timing = 0;
+    double graph_tol = 0.0;
+    hipStream_t graph_stream = nullptr;
+    std::vector<hipEvent_t> ev;  // with timing: a start/stop pair around every captured sweep
+
+    ~Plan()
+    {
+        if (gexec) (void)hipGraphExecDestroy(gexec);
+        if (graph) (void)hipGraphDestroy(graph);
+        for (auto e : ev) (void)hipEventDestroy(e);
+    }
+
+    SweepArgs sweep_args(int mode_all, int psi_mode) const
+    {
+        SweepArgs a{};
+        a.probs = d_probs.as<ProblemDev>();
+        a.ws = d_ws.as<WaveStreamDev>();
+        a.lanes = d_lanes.as<LaneDev>();
+        a.sys = d_sys.as<SystemDev>();
+        a.tickets = d_tickets.as<int2>();
+        a.ntickets = ntickets;
+        a.spin_limit = 1 << 24;
+        a.mode_all = mode_all;
+        a.sigma_t = d_st.p;
+        a.src = d_src.p;
+        a.ang_src = d_ang.p;
+        a.psi_out = d_psi.p;
+        a.part = d_part.p;
+        a.slot_off = d_slot_off.as<int64_t>();
+        a.edge = d_edge.p;
+        a.inflow = d_inflow.p;
+        a.prog = d_prog.as<long long>();
+        a.ctl = d_ctl.as<Ctl>();
+        a.sysctl = d_sysctl.as<SysCtl>();
+        (void)psi_mode;
+        return a;
+    }
+
+    CombineArgs combine_args(int mode, double tol) const
+    {
+        CombineArgs c{};
+        c.sys = d_sys.as<SystemDev>();
+        c.probs = d_probs.as<ProblemDev>();
+        c.slot_order = d_slot_order.as<int32_t>();
+        c.slot_off = d_slot_off.as<int64_t>();
+        c.blocks = d_cblocks.as<int2>();
+        c.cells_per_block = cells_per_block;
+        c.nsys = nsys;
+        c.mode = mode;
+        c.max_iter = max_iter;
+        c.tol = tol;
+        c.part = d_part.p;
+        c.phi = d_phi.p;
+        c.src = d_src.p;
+        c.sigma_s = d_ss.p;
+        c.q = d_q.p;
+        c.sysctl = d_sysctl.as<SysCtl>();
+        c.ctl = d_ctl.as<Ctl>();
+        c.rhist = d_rhist.as<double>();
+        return c;
+    }
+};
+
+rom_handle::~rom_handle()
+{
+    plan.reset();
+    if (own_stream) (void)hipStreamDestroy(own_stream);
+}
+
+namespace {
+
+int device_cus()
+{
+    static int cus = 0;
+    if (!cus) {
+        int dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+            cus = 256;
+    }
+    return cus;
+}
+
+void choose_tiles(const rom_si_opts& o, const std::vector<SysInput>& in, bool fp64, int& tx, int& ty)
+{
+    if (o.tile_x > 0 && o.tile_y > 0) {
+        tx = o.tile_x;
+        ty = o.tile_y;
+        return;
+    }
+    // Heuristic: enough strips in flight to cover the GPU, chunks wide enough to amortise the
+    // hand-off.  Double precision keeps 8 x 8 (register pressure).
+    int64_t work = 0;
+    int maxside = 0;
+    for (auto& s : in) {
+        work += (int64_t)s.h->cells * s.n;
+        maxside = std::max(maxside, std::max(s.h->grid.nx, s.h->grid.ny));
+    }
+    if (fp64) {
+        tx = 8;
+        ty = 8;
+        return;
+    }
+    if (in.size() == 1 && maxside <= 512) {
+        tx = 8;
+        ty = 4;
+    } else {
+        tx = 16;
+        ty = 16;
+    }
+}
+
+// Build every table and buffer of a plan for the given systems.
+void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, bool aniso, int max_iter)
+{
+    P.fp64 = o.precision == ROM_PREC_FP64;
+    P.dd = o.scheme == ROM_SCHEME_DD;
+    P.aniso = aniso;
+    P.esz = P.fp64 ? 8 : 4;
+    P.max_iter = max_iter;
+    choose_tiles(o, in, P.fp64, P.tx, P.ty);
+    if (!sweep_tile_supported(P.tx, P.ty)) throw Fail{ROM_E_ARG, "unsupported tile shape"};
+    const int TX = P.tx, TY = P.ty;
+
+    // problems = distinct handles, in first-appearance order
+    std::map<rom_handle*, int> pidx;
+    for (auto& s : in)
+        if (!pidx.count(s.h)) {
+            pidx[s.h] = (int)P.handles.size();
+            P.handles.push_back(s.h);
+        }
+    const int nprob = (int)P.handles.size();
+    std::vector<int64_t> field_off(nprob);
+    int64_t fsum = 0;
+    for (int p = 0; p < nprob; ++p) {
+        rom_handle* h = P.handles[p];
+        ProblemDev pd{};
+        pd.nx = h->grid.nx;
+        pd.ny = h->grid.ny;
+        pd.nchunks = (pd.nx + TX - 1) / TX;
+        pd.nstrips = (pd.ny + TY - 1) / TY;
+        pd.field_off = fsum;
+        field_off[p] = fsum;
+        fsum += h->cells;
+        P.probs.push_back(pd);
+    }
+
+    // lanes per group: smallest of 16/32/64 covering the largest per-quadrant count of a problem
+    std::vector<int> Lp(nprob, 16);
+    struct QuadList {
+        std::vector<int> idx[4];
+    };
+    std::vector<QuadList> ql(in.size());
+    for (size_t k = 0; k < in.size(); ++k) {
+        for (int l = 0; l < in[k].n; ++l) ql[k].idx[quadrant_of(in[k].dirs[3 * l], in[k].dirs[3 * l + 1])].push_back(l);
+        const int p = pidx[in[k].h];
+        for (int q = 0; q < 4; ++q) {
+            const int m = (int)ql[k].idx[q].size();
+            while (Lp[p] < 64 && Lp[p] < m) Lp[p] *= 2;
+        }
+    }
+
+    // systems: internal (quadrant-grouped, padded) ordinate order
+    P.nsys = (int)in.size();
+    P.sys.resize(P.nsys);
+    P.user_of.resize(P.nsys);
+    P.sys_n.resize(P.nsys);
+    P.sys_w.resize(P.nsys);
+    P.npad_al.resize(P.nsys);
+    struct Group {
+        int sys, quad, first;  // first internal index
+        int count;             // real ordinates in the group
+    };
+    std::vector<std::vector<Group>> groups_pq(nprob * 4);
+    int64_t phi_sum = 0, ang_sum = 0;
+    for (int s = 0; s < P.nsys; ++s) {
+        const int p = pidx[in[s].h];
+        const int L = Lp[p];
+        std::vector<int>& uo = P.user_of[s];
+        for (int q = 0; q < 4; ++q) {
+            const auto& list = ql[s].idx[q];
+            for (size_t b = 0; b < list.size(); b += L) {
+                Group g{s, q, (int)uo.size(), (int)std::min<size_t>(L, list.size() - b)};
+                groups_pq[p * 4 + q].push_back(g);
+                for (int k = 0; k < L; ++k) uo.push_back(b + k < list.size() ? list[b + k] : -1);
+            }
+        }
+        const int npad = (int)uo.size();
+        const int al = aniso ? ((npad + 127) / 128) * 128 : npad;
+        P.npad_al[s] = al;
+        SystemDev& sd = P.sys[s];
+        sd.prob = p;
+        sd.npad = al;
+        sd.phi_off = phi_sum;
+        sd.src_off = phi_sum;
+        sd.ang_off = ang_sum;
+        phi_sum += in[s].h->cells;
+        if (aniso) ang_sum += in[s].h->cells * (int64_t)al;
+        P.sys_n[s] = in[s].n;
+        P.sys_w[s] = in[s].w;
+    }
+
+    // wave-streams, slots
+    int64_t part_sum = 0, edge_sum = 0, inflow_sum = 0;
+    int prog_sum = 0;
+    std::vector<std::vector<int>> sys_slots(P.nsys);
+    for (int p = 0; p < nprob; ++p) {
+        rom_handle* h = P.handles[p];
+        const int L = Lp[p], G = 64 / L;
+        const ProblemDev& pd = P.probs[p];
+        bool vacuum = true;
+        for (int f = 0; f < 4; ++f)
+            if (!h->face[f].empty()) vacuum = false;
+        for (auto& s : in)
+            if (s.h == h && s.use_angular)
+                for (int f = 0; f < 4; ++f)
+                    if (!h->ang[f].empty()) vacuum = false;
+        for (int q = 0; q < 4; ++q) {
+            auto& gl = groups_pq[p * 4 + q];
+            for (size_t g0 = 0; g0 < gl.size(); g0 += G) {
+                WaveStreamDev W{};
+                W.prob = p;
+                W.quad = q;
+                W.L = L;
+                W.prog_off = prog_sum;
+                prog_sum += pd.nstrips;
+                W.edge_off = edge_sum;
+                edge_sum += (int64_t)pd.nstrips * pd.nx * kWave;
+                W.xin_off = W.yin_off = -1;
+                if (!vacuum) {
+                    W.xin_off = inflow_sum;
+                    inflow_sum += (int64_t)pd.ny * kWave;
+                    W.yin_off = inflow_sum;
+                    inflow_sum += (int64_t)pd.nx * kWave;
+                }
+                for (int k = 0; k < kMaxGroups; ++k) {
+                    W.sys[k] = -1;
+                    W.slot[k] = -1;
+                }
+                const int wsi = (int)P.ws.size();
+                for (int k = 0; k < G; ++k) {
+                    LaneDev pad{};
+                    if (g0 + k < gl.size()) {
+                        const Group& gr = gl[g0 + k];
+                        W.sys[k] = gr.sys;
+                        W.slot[k] = P.nslots;
+                        P.slot_off.push_back(part_sum);
+                        part_sum += h->cells;
+                        sys_slots[gr.sys].push_back(P.nslots);
+                        ++P.nslots;
+                        const SysInput& si = in[gr.sys];
+                        for (int l = 0; l < L; ++l) {
+                            LaneDev ld{};
+                            ld.ord = gr.first + l;
+                            const int u = P.user_of[gr.sys][gr.first + l];
+                            if (u >= 0) {
+                                ld.a = std::fabs(si.dirs[3 * u]) / h->dx;
+                                ld.b = std::fabs(si.dirs[3 * u + 1]) / h->dy;
+                                ld.w = si.w[u];
+                            }
+                            P.lanes.push_back(ld);
+                        }
+                    } else {
+                        for (int l = 0; l < L; ++l) P.lanes.push_back(pad);
+                    }
+                }
+                (void)wsi;
+                P.ws.push_back(W);
+            }
+        }
+    }
+    P.nws = (int)P.ws.size();
+    // fixed summation order of each system's partial fluxes: quadrant-major, block order
+    for (int s = 0; s < P.nsys; ++s) {
+        P.sys[s].slot_first = (int)P.slot_order.size();
+        P.sys[s].nslots = (int)sys_slots[s].size();
+        std::vector<std::pair<int, int>> key;
+        for (int sl : sys_slots[s]) key.push_back({sl, sl});
+        std::sort(key.begin(), key.end());
+        for (auto& kv : key) P.slot_order.push_back(kv.second);
+    }
+    // tickets: strip-major, so every strip's producer precedes it
+    int maxstrips = 0;
+    for (auto& pd : P.probs) maxstrips = std::max(maxstrips, pd.nstrips);
+    for (int st = 0; st < maxstrips; ++st)
+        for (int k = 0; k < P.nws; ++k)
+            if (st < P.probs[P.ws[k].prob].nstrips) P.tickets.push_back(make_int2(k, st));
+    P.ntickets = (int)P.tickets.size();
+    P.grid = std::max(1, std::min(P.ntickets, device_cus() * 8));
+    // combine blocks
+    for (int s = 0; s < P.nsys; ++s)
+        for (int64_t c0 = 0; c0 < in[s].h->cells; c0 += P.cells_per_block) P.cblocks.push_back(make_int2(s, (int)c0));
+
+    // ---- device buffers
+    upload(P.d_probs, P.probs);
+    upload(P.d_sys, P.sys);
+    upload(P.d_ws, P.ws);
+    upload(P.d_lanes, P.lanes);
+    upload(P.d_tickets, P.tickets);
+    upload(P.d_slot_off, P.slot_off);
+    upload(P.d_slot_order, P.slot_order);
+    upload(P.d_cblocks, P.cblocks);
+
+    auto cast_upload = [&](DevMem& d, const std::vector<double>& v) {
+        if (P.fp64) {
+            upload(d, v);
+        } else {
+            std::vector<float> f(v.begin(), v.end());
+            upload(d, f);
+        }
+    };
+    std::vector<double> st(fsum), ss(fsum), qv(fsum);
+    for (int p = 0; p < nprob; ++p) {
+        rom_handle* h = P.handles[p];
+        std::copy(h->st.begin(), h->st.end(), st.begin() + field_off[p]);
+        std::copy(h->ss.begin(), h->ss.end(), ss.begin() + field_off[p]);
+        std::copy(h->q.begin(), h->q.end(), qv.begin() + field_off[p]);
+    }
+    cast_upload(P.d_st, st);
+    cast_upload(P.d_ss, ss);
+    cast_upload(P.d_q, qv);
+
+    // inflow in sweep order, scaled by the lane weight
+    if (inflow_sum > 0) {
+        std::vector<double> inf(inflow_sum, 0.0);
+        for (int k = 0; k < P.nws; ++k) {
+            const WaveStreamDev& W = P.ws[k];
+            if (W.xin_off < 0) continue;
+            rom_handle* h = P.handles[W.prob];
+            const int nx = h->grid.nx, ny = h->grid.ny;
+            const bool xpos = (W.quad == 0 || W.quad == 3), ypos = (W.quad < 2);
+            const int fx = xpos ? ROM_FACE_LEFT : ROM_FACE_RIGHT;
+            const int fy = ypos ? ROM_FACE_BOTTOM : ROM_FACE_TOP;
+            for (int lane = 0; lane < kWave; ++lane) {
+                const int gi = lane / W.L;
+                const int s = W.sys[gi];
+                if (s < 0) continue;
+                const LaneDev& ld = P.lanes[(size_t)k * kWave + lane];
+                const int u = P.user_of[s][ld.ord];
+                if (u < 0) continue;
+                const bool angok = in[s].use_angular;
+                for (int jj = 0; jj < ny; ++jj) {
+                    const int j = ypos ? jj : ny - 1 - jj;
+                    double v = 0.0;
+                    if (angok && !h->ang[fx].empty()) v = h->ang[fx][(size_t)u * ny + j];
+                    else if (!h->face[fx].empty()) v = h->face[fx][j];
+                    inf[W.xin_off + (int64_t)jj * kWave + lane] = ld.w * v;
+                }
+                for (int ii = 0; ii < nx; ++ii) {
+                    const int i = xpos ? ii : nx - 1 - ii;
+                    double v = 0.0;
+                    if (angok && !h->ang[fy].empty()) v = h->ang[fy][(size_t)u * nx + i];
+                    else if (!h->face[fy].empty()) v = h->face[fy][i];
+                    inf[W.yin_off + (int64_t)ii * kWave + lane] = ld.w * v;
+                }
+            }
+        }
+        cast_upload(P.d_inflow, inf);
+    } else {
+        HIPCHK(P.d_inflow.alloc(256));
+    }
+
+    HIPCHK(P.d_src.alloc(phi_sum * P.esz));
+    HIPCHK(P.d_phi.alloc(phi_sum * P.esz));
+    HIPCHK(P.d_part.alloc(std::max<int64_t>(part_sum, 1) * P.esz));
+    HIPCHK(P.d_edge.alloc(std::max<int64_t>(edge_sum, 1) * P.esz));
+    HIPCHK(P.d_prog.alloc(std::max(prog_sum, 1) * sizeof(long long)));
+    HIPCHK(hipMemset(P.d_prog.p, 0, std::max(prog_sum, 1) * sizeof(long long)));
+    HIPCHK(P.d_ctl.alloc(sizeof(Ctl)));
+    HIPCHK(hipMemset(P.d_ctl.p, 0, sizeof(Ctl)));
+    HIPCHK(P.d_sysctl.alloc(P.nsys * sizeof(SysCtl)));
+    HIPCHK(hipMemset(P.d_sysctl.p, 0, P.nsys * sizeof(SysCtl)));
+    if (max_iter > 0) HIPCHK(P.d_rhist.alloc((size_t)P.nsys * max_iter * sizeof(double)));
+    if (aniso) {
+        HIPCHK(P.d_ang.alloc(std::max<int64_t>(ang_sum, 1) * P.esz));
+        HIPCHK(P.d_psi.alloc(std::max<int64_t>(ang_sum, 1) * (P.fp64 ? 8 : 2)));
+    }
+}
+
+// P^T in internal order for every system: Bt[n][k] = P(u_k, u_n), zero on padding.
+void build_kernel_matrices(Plan& P, const std::vector<SysInput>& in)
+{
+    int64_t total = 0;
+    P.pt_off.resize(P.nsys);
+    for (int s = 0; s < P.nsys; ++s) {
+        P.pt_off[s] = total;
+        total += (int64_t)P.npad_al[s] * P.npad_al[s];
+    }
+    std::vector<double> bt64;
+    std::vector<uint16_t> bt16;
+    if (P.fp64) bt64.assign(total, 0.0);
+    else bt16.assign(total, 0);
+    for (int s = 0; s < P.nsys; ++s) {
+        rom_handle* h = in[s].h;
+        const int al = P.npad_al[s];
+        const auto& uo = P.user_of[s];
+        const int npad = (int)uo.size();
+        for (int nn = 0; nn < npad; ++nn) {
+            const int un = uo[nn];
+            if (un < 0) continue;
+            for (int kk = 0; kk < npad; ++kk) {
+                const int uk = uo[kk];
+                if (uk < 0) continue;
+                double pv;
+                if (h->scat == ROM_SCAT_DENSE) pv = h->Pdense[(size_t)uk * h->n + un];
+                else pv = phase_folded(h->scat, h->g, in[s].dirs + 3 * uk, in[s].dirs + 3 * un);
+                const int64_t idx = P.pt_off[s] + (int64_t)nn * al + kk;
+                if (P.fp64) bt64[idx] = pv;
+                else bt16[idx] = f32_to_bf16((float)pv);
+            }
+        }
+    }
+    if (P.fp64) upload(P.d_Pt, bt64);
+    else upload(P.d_Pt, bt16);
+}
+
+void enqueue_iteration(Plan& P, hipStream_t s, double tol, hipEvent_t e_start = nullptr, hipEvent_t e_stop = nullptr)
+{
+    if (P.aniso) {
+        for (int k = 0; k < P.nsys; ++k) {
+            const SystemDev& sd = P.sys[k];
+            ContractArgs c{};
+            c.a = (const char*)P.d_psi.p + sd.ang_off * (P.fp64 ? 8 : 2);
+            c.bt = (const char*)P.d_Pt.p + P.pt_off[k] * (P.fp64 ? 8 : 2);
+            c.sigma_s = (const char*)P.d_ss.p + P.probs[sd.prob].field_off * P.esz;
+            c.q = (const char*)P.d_q.p + P.probs[sd.prob].field_off * P.esz;
+            c.out = (char*)P.d_ang.p + sd.ang_off * P.esz;
+            c.M = (int)P.handles[sd.prob]->cells;
+            c.N = c.K = P.npad_al[k];
+            c.sys_index = k;
+            c.sysctl = P.d_sysctl.as<SysCtl>();
+            HIPCHK(launch_contract(c, P.fp64 ? 2 : 0, s));
+        }
+    }
+    const SweepArgs sa = P.sweep_args(0, 0);
+    if (e_start) HIPCHK(hipEventRecord(e_start, s));
+    HIPCHK(launch_sweep(sa, P.grid, P.fp64, P.tx, P.ty, P.dd, P.aniso, P.aniso ? (P.fp64 ? 1 : 2) : 0, s));
+    if (e_stop) HIPCHK(hipEventRecord(e_stop, s));
+    const CombineArgs ca = P.combine_args(0, tol);
+    HIPCHK(launch_combine(ca, (int)P.cblocks.size(), P.fp64, s));
+}
+
+struct SolveResult {
+    std::vector<SysCtl> sc;
+    bool error = false;
+    double ms = 0;
+    double sweep_ms = 0;
+    int sweeps = 0;
+};
+
+// Source iteration for every system of the plan.  The first iterate starts from phi = 0 (so the
+// first source is q), the per-iteration kernels are captured once in a graph of K iterations
+// and replayed until every system has stopped.
+SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
+{
+    const double tol = o.tol;
+    int K = o.iters_per_check > 0 ? o.iters_per_check : 0;
+    if (K == 0) K = P.max_iter <= 64 ? 4 : 8;
+    K = std::min(K, P.max_iter);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    // initial state: phi = 0, isotropic source = q, angular flux = 0
+    int64_t phi_total = 0;
+    for (auto& sd : P.sys) phi_total = std::max<int64_t>(phi_total, sd.phi_off + P.handles[sd.prob]->cells);
+    HIPCHK(launch_fill(P.d_phi.p, phi_total, P.fp64, 0.0, s));
+    for (auto& sd : P.sys) {
+        const int64_t cells = P.handles[sd.prob]->cells;
+        HIPCHK(hipMemcpyAsync((char*)P.d_src.p + sd.src_off * P.esz, (char*)P.d_q.p + P.probs[sd.prob].field_off * P.esz,
+                              cells * P.esz, hipMemcpyDeviceToDevice, s));
+    }
+    if (P.aniso) {
+        int64_t tot = 0;
+        for (int k = 0; k < P.nsys; ++k) tot = std::max<int64_t>(tot, P.sys[k].ang_off + P.handles[P.sys[k].prob]->cells * (int64_t)P.npad_al[k]);
+        if (P.fp64) HIPCHK(launch_fill(P.d_psi.p, tot, true, 0.0, s));
+        else HIPCHK(launch_fill(P.d_psi.p, (tot + 1) / 2, false, 0.0, s));  // BF16 zeros are float zeros
+    }
+    HIPCHK(launch_reset_systems(P.d_sysctl.as<SysCtl>(), P.nsys, P.d_ctl.as<Ctl>(), s));
+
+    const int timing = o.timing ? 1 : 0;
+    if (!P.gexec || P.graph_iters != K || P.graph_stream != s || P.graph_timing != timing || P.graph_tol != tol) {
+        if (P.gexec) {
+            (void)hipGraphExecDestroy(P.gexec);
+            P.gexec = nullptr;
+        }
+        if (P.graph) {
+            (void)hipGraphDestroy(P.graph);
+            P.graph = nullptr;
+        }
+        for (auto e : P.ev) (void)hipEventDestroy(e);
+        P.ev.clear();
+        if (timing) {
+            P.ev.resize(2 * K);
+            for (auto& e : P.ev) HIPCHK(hipEventCreate(&e));
+        }
+        HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+        try {
+            for (int k = 0; k < K; ++k)
+                enqueue_iteration(P, s, tol, timing ? P.ev[2 * k] : nullptr, timing ? P.ev[2 * k + 1] : nullptr);
+        } catch (...) {
+            hipGraph_t g;
+            (void)hipStreamEndCapture(s, &g);
+            if (g) (void)hipGraphDestroy(g);
+            throw;
+        }
+        HIPCHK(hipStreamEndCapture(s, &P.graph));
+        HIPCHK(hipGraphInstantiate(&P.gexec, P.graph, nullptr, nullptr, 0));
+        P.graph_iters = K;
+        P.graph_stream = s;
+        P.graph_timing = timing;
+        P.graph_tol = tol;
+    }
+    Ctl ctl{};
+    int launched = 0;
+    double sweep_ms = 0.0;
+    int sweeps = 0;
+    int active_before = P.nsys;
+    for (;;) {
+        HIPCHK(hipGraphLaunch(P.gexec, s));
+        launched += K;
+        HIPCHK(hipMemcpyAsync(&ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (timing && active_before > 0) {
+            // sweeps of an already finished solve return at once; count the ones that ran
+            for (int k = 0; k < K; ++k) {
+                float t = 0.f;
+                HIPCHK(hipEventElapsedTime(&t, P.ev[2 * k], P.ev[2 * k + 1]));
+                sweep_ms += t;
+                ++sweeps;
+            }
+        }
+        active_before = ctl.active;
+        if (ctl.error || ctl.active == 0 || launched >= P.max_iter + K) break;
+    }
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    SolveResult r;
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    r.ms = ms;
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    r.error = ctl.error != 0;
+    r.sweep_ms = sweep_ms;
+    r.sweeps = sweeps;
+    r.sc.resize(P.nsys);
+    HIPCHK(hipMemcpy(r.sc.data(), P.d_sysctl.p, P.nsys * sizeof(SysCtl), hipMemcpyDeviceToHost));
+    return r;
+}
+
+void download_phi(const Plan& P, int sys, double* out)
+{
+    const SystemDev& sd = P.sys[sys];
+    const int64_t cells = P.handles[sd.prob]->cells;
+    if (P.fp64) {
+        HIPCHK(hipMemcpy(out, (const char*)P.d_phi.p + sd.phi_off * 8, cells * 8, hipMemcpyDeviceToHost));
+    } else {
+        std::vector<float> tmp(cells);
+        HIPCHK(hipMemcpy(tmp.data(), (const char*)P.d_phi.p + sd.phi_off * 4, cells * 4, hipMemcpyDeviceToHost));
+        for (int64_t k = 0; k < cells; ++k) out[k] = tmp[k];
+    }
+}
+
+int validate_opts(rom_handle* h, const rom_si_opts* o, rom_si_opts& out)
+{
+    std::memset(&out, 0, sizeof(out));
+    if (o) out = *o;
+    if (!isfin(out.tol)) return fail(h, ROM_E_ARG, "tol must be finite");
+    if (out.tol == 0.0) out.tol = 1e-6;
+    if (out.max_iter < 0) return fail(h, ROM_E_ARG, "max_iter must be >= 0");
+    if (out.max_iter == 0) out.max_iter = 1000;
+    if (out.precision != ROM_PREC_FP32 && out.precision != ROM_PREC_FP64) return fail(h, ROM_E_ARG, "bad precision");
+    if (out.scheme != ROM_SCHEME_STEP && out.scheme != ROM_SCHEME_DD) return fail(h, ROM_E_ARG, "bad scheme");
+    if (out.iters_per_check < 0) return fail(h, ROM_E_ARG, "iters_per_check must be >= 0");
+    if (out.contract_split != 0) return fail(h, ROM_E_UNSUPPORTED, "split contraction is not built");
+    if ((out.tile_x != 0 || out.tile_y != 0) && !sweep_tile_supported(out.tile_x, out.tile_y))
+        return fail(h, ROM_E_ARG, "unsupported tile shape (8x4, 8x8, 16x8, 16x16, 32x16)");
+    return ROM_OK;
+}
+
+std::string plan_signature(const rom_si_opts& o, bool aniso, int kind, int nsys)
+{
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "k%d p%d s%d t%dx%d a%d n%d mi%d", kind, o.precision, o.scheme, o.tile_x, o.tile_y,
+                  (int)aniso, nsys, o.max_iter);
+    return buf;
+}
+
+int check_ordinates(rom_handle* h, int n, const double* dirs, const double* w)
+{
+    if (n <= 0 || !dirs || !w) return fail(h, ROM_E_ARG, "ordinates: n must be > 0 and arrays non-NULL");
+    double sw = 0.0;
+    for (int l = 0; l < n; ++l) {
+        const double c = dirs[3 * l], s = dirs[3 * l + 1], z = dirs[3 * l + 2];
+        if (!isfin(c) || !isfin(s) || !isfin(z) || !isfin(w[l]))
+            return fail(h, ROM_E_DOMAIN, "ordinates: non-finite value at index " + std::to_string(l));
+        if (std::fabs(c * c + s * s + z * z - 1.0) > 1e-12)
+            return fail(h, ROM_E_DOMAIN, "ordinates: direction " + std::to_string(l) + " is not a unit vector");
+        if (!(w[l] > 0.0)) return fail(h, ROM_E_DOMAIN, "ordinates: weights must be > 0");
+        sw += w[l];
+    }
+    if (std::fabs(sw - 1.0) > 1e-12) return fail(h, ROM_E_DOMAIN, "ordinates: weights must sum to 1");
+    return ROM_OK;
+}
+
+}  // namespace
+
+// ====================================================================================== C ABI
+extern "C" {
+
+const char* rom_version(void) { return "librom 0.1 (gfx950)"; }
+
+const char* rom_status_string(int st)
+{
+    switch (st) {
+    case ROM_OK: return "ok";
+    case ROM_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case ROM_E_ARG: return "invalid argument";
+    case ROM_E_DOMAIN: return "input outside the problem domain";
+    case ROM_E_STATE: return "call out of order";
+    case ROM_E_NOMEM: return "out of memory";
+    case ROM_E_DEVICE: return "device error";
+    case ROM_E_DIVERGED: return "iteration diverged";
+    case ROM_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+    }
+}
+
+const char* rom_last_error(const rom_handle* h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int32_t rom_ordinate_count(const rom_ord_spec* spec) { return spec ? ordinate_count(*spec) : -1; }
+
+int rom_generate_ordinates(const rom_ord_spec* spec, uint64_t seed, int64_t sample, double* dirs, double* w)
+{
+    if (!spec || !dirs || !w || sample < 0) return ROM_E_ARG;
+    if (ordinate_count(*spec) <= 0) return ROM_E_ARG;
+    return generate_ordinates(*spec, seed, sample, dirs, w);
+}
+
+int rom_create(const rom_grid* grid, const double* sigma_t, const double* sigma_s, const double* q,
+               const rom_inflow* inflow, rom_handle** out)
+{
+    if (!out) return fail(nullptr, ROM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!grid || !sigma_t || !sigma_s || !q) return fail(nullptr, ROM_E_ARG, "NULL grid or field");
+    if (grid->nx <= 0 || grid->ny <= 0) return fail(nullptr, ROM_E_ARG, "nx, ny must be positive");
+    if ((int64_t)grid->nx * grid->ny > (int64_t)1 << 31) return fail(nullptr, ROM_E_ARG, "grid too large");
+    if (!isfin(grid->x0) || !isfin(grid->x1) || !isfin(grid->y0) || !isfin(grid->y1) || !(grid->x1 > grid->x0) ||
+        !(grid->y1 > grid->y0))
+        return fail(nullptr, ROM_E_ARG, "grid box must satisfy x1 > x0, y1 > y0");
+    const int64_t cells = (int64_t)grid->nx * grid->ny;
+    for (int64_t k = 0; k < cells; ++k) {
+        const double st = sigma_t[k], ss = sigma_s[k], qq = q[k];
+        if (!isfin(st) || !isfin(ss) || !isfin(qq)) return fail(nullptr, ROM_E_DOMAIN, "non-finite field value");
+        if (!(st > 0.0)) return fail(nullptr, ROM_E_DOMAIN, "sigma_t must be > 0");
+        if (ss < 0.0) return fail(nullptr, ROM_E_DOMAIN, "sigma_s must be >= 0");
+        if (!(ss < st)) return fail(nullptr, ROM_E_DOMAIN, "sigma_s must be < sigma_t");
+        if (qq < 0.0) return fail(nullptr, ROM_E_DOMAIN, "q must be >= 0");
+    }
+    const double* faces[4] = {inflow ? inflow->left : nullptr, inflow ? inflow->right : nullptr,
+                              inflow ? inflow->bottom : nullptr, inflow ? inflow->top : nullptr};
+    for (int f = 0; f < 4; ++f) {
+        if (!faces[f]) continue;
+        const int len = f < 2 ? grid->ny : grid->nx;
+        for (int k = 0; k < len; ++k)
+            if (!isfin(faces[f][k]) || faces[f][k] < 0.0) return fail(nullptr, ROM_E_DOMAIN, "inflow must be finite and >= 0");
+    }
+    std::unique_ptr<rom_handle> h(new (std::nothrow) rom_handle());
+    if (!h) return fail(nullptr, ROM_E_NOMEM, "host allocation failed");
+    try {
+        h->grid = *grid;
+        h->dx = (grid->x1 - grid->x0) / grid->nx;
+        h->dy = (grid->y1 - grid->y0) / grid->ny;
+        h->cells = cells;
+        h->st.assign(sigma_t, sigma_t + cells);
+        h->ss.assign(sigma_s, sigma_s + cells);
+        h->q.assign(q, q + cells);
+        for (int f = 0; f < 4; ++f)
+            if (faces[f]) h->face[f].assign(faces[f], faces[f] + (f < 2 ? grid->ny : grid->nx));
+        // device work is deferred to the first solve, so a handle can be built and validated
+        // on a host without a GPU; a missing device surfaces there as ROM_E_DEVICE
+        if (hipGetDevice(&h->device) != hipSuccess) h->device = -1;
+    } catch (const std::bad_alloc&) {
+        return fail(nullptr, ROM_E_NOMEM, "host allocation failed");
+    }
+    *out = h.release();
+    return ROM_OK;
+}
+
+void rom_destroy(rom_handle* h) { delete h; }
+
+int rom_set_stream(rom_handle* h, void* stream)
+{
+    if (!h) return ROM_E_ARG;
+    h->user_stream = (hipStream_t)stream;
+    return ROM_OK;
+}
+
+int rom_set_ordinates(rom_handle* h, int32_t n, const double* dirs, const double* w)
+{
+    if (!h) return ROM_E_ARG;
+    int rc = check_ordinates(h, n, dirs, w);
+    if (rc) return rc;
+    h->n = n;
+    h->dirs.assign(dirs, dirs + 3 * (size_t)n);
+    h->w.assign(w, w + n);
+    for (auto& a : h->ang) a.clear();
+    if (h->scat == ROM_SCAT_DENSE) {
+        h->scat = ROM_SCAT_ISO;
+        h->Pdense.clear();
+    }
+    h->version++;
+    return ROM_OK;
+}
+
+int rom_set_inflow_angular(rom_handle* h, int32_t face, const double* vals)
+{
+    if (!h) return ROM_E_ARG;
+    if (face < 0 || face > 3) return fail(h, ROM_E_ARG, "bad face");
+    if (h->n == 0) return fail(h, ROM_E_STATE, "set ordinates before angular inflow");
+    if (!vals) {
+        h->ang[face].clear();
+        h->version++;
+        return ROM_OK;
+    }
+    const size_t len = (size_t)h->n * (face < 2 ? h->grid.ny : h->grid.nx);
+    for (size_t k = 0; k < len; ++k)
+        if (!isfin(vals[k]) || vals[k] < 0.0) return fail(h, ROM_E_DOMAIN, "inflow must be finite and >= 0");
+    h->ang[face].assign(vals, vals + len);
+    h->version++;
+    return ROM_OK;
+}
+
+int rom_set_scattering(rom_handle* h, int32_t kind, double g, const double* P)
+{
+    if (!h) return ROM_E_ARG;
+    if (kind < ROM_SCAT_ISO || kind > ROM_SCAT_DENSE) return fail(h, ROM_E_ARG, "bad scattering kind");
+    if (!isfin(g)) return fail(h, ROM_E_DOMAIN, "g must be finite");
+    if (kind == ROM_SCAT_HG && !(std::fabs(g) < 1.0)) return fail(h, ROM_E_DOMAIN, "HG needs |g| < 1");
+    if (kind == ROM_SCAT_LINEAR && !(std::fabs(g) <= 1.0)) return fail(h, ROM_E_DOMAIN, "linear kernel needs |g| <= 1");
+    if (kind == ROM_SCAT_DENSE) {
+        if (h->n == 0) return fail(h, ROM_E_STATE, "set ordinates before a dense kernel");
+        if (!P) return fail(h, ROM_E_ARG, "dense kernel needs P");
+        const size_t nn = (size_t)h->n * h->n;
+        for (size_t k = 0; k < nn; ++k)
+            if (!isfin(P[k]) || P[k] < 0.0) return fail(h, ROM_E_DOMAIN, "P must be finite and >= 0");
+        h->Pdense.assign(P, P + nn);
+    } else {
+        h->Pdense.clear();
+    }
+    h->scat = kind;
+    h->g = g;
+    h->version++;
+    return ROM_OK;
+}
+
+int rom_phi_device(const rom_handle* h, const void** dev, int32_t* is_fp64)
+{
+    if (!h || !dev || !is_fp64) return ROM_E_ARG;
+    if (!h->res_dev) return ROM_E_STATE;
+    *dev = h->res_dev;
+    *is_fp64 = h->res_fp64 ? 1 : 0;
+    return ROM_OK;
+}
+
+int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double* phi, double* psi,
+              const rom_si_opts* opts)
+{
+    if (!h) return ROM_E_ARG;
+    if (!src || !phi) return fail(h, ROM_E_ARG, "src and phi must be non-NULL");
+    if (h->n == 0) return fail(h, ROM_E_STATE, "set ordinates first");
+    rom_si_opts o;
+    int rc = validate_opts(h, opts, o);
+    if (rc) return rc;
+    try {
+        const bool per = src_per_ordinate != 0;
+        const size_t nsrc = per ? (size_t)h->n * h->cells : (size_t)h->cells;
+        for (size_t k = 0; k < nsrc; ++k)
+            if (!isfin(src[k])) return fail(h, ROM_E_DOMAIN, "non-finite source");
+        std::vector<SysInput> in{{h, h->dirs.data(), h->w.data(), h->n, true}};
+        std::unique_ptr<Plan> P(new Plan());
+        build_plan(*P, in, o, per, 0);
+        hipStream_t s = h->stream();
+        const SystemDev& sd = P->sys[0];
+        const int al = P->npad_al[0];
+        if (per) {
+            // per-ordinate source in the internal [cells][npad] layout
+            std::vector<double> a((size_t)h->cells * al, 0.0);
+            for (int k = 0; k < al && k < (int)P->user_of[0].size(); ++k) {
+                const int u = P->user_of[0][k];
+                if (u < 0) continue;
+                for (int64_t c = 0; c < h->cells; ++c) a[(size_t)c * al + k] = src[(size_t)u * h->cells + c];
+            }
+            if (P->fp64) upload(P->d_ang, a);
+            else {
+                std::vector<float> f(a.begin(), a.end());
+                upload(P->d_ang, f);
+            }
+        } else {
+            if (P->fp64) HIPCHK(hipMemcpy(P->d_src.p, src, h->cells * 8, hipMemcpyHostToDevice));
+            else {
+                std::vector<float> f(src, src + h->cells);
+                HIPCHK(hipMemcpy(P->d_src.p, f.data(), h->cells * 4, hipMemcpyHostToDevice));
+            }
+        }
+        const int psi_mode = psi ? 1 : 0;
+        if (psi) {
+            const int64_t tot = h->cells * (int64_t)al;
+            HIPCHK(P->d_psi.alloc(tot * P->esz));
+        }
+        HIPCHK(launch_reset_systems(P->d_sysctl.as<SysCtl>(), 1, P->d_ctl.as<Ctl>(), s));
+        SweepArgs sa = P->sweep_args(1, psi_mode);
+        // the sweep writes psi' into the angular layout when asked for it
+        HIPCHK(launch_sweep(sa, P->grid, P->fp64, P->tx, P->ty, P->dd, per, psi_mode, s));
+        const CombineArgs ca = P->combine_args(1, 0.0);
+        HIPCHK(launch_combine(ca, (int)P->cblocks.size(), P->fp64, s));
+        Ctl ctl{};
+        HIPCHK(hipMemcpyAsync(&ctl, P->d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (ctl.error) return fail(h, ROM_E_DEVICE, "sweep dependency wait timed out");
+        download_phi(*P, 0, phi);
+        if (psi) {
+            const int64_t tot = h->cells * (int64_t)al;
+            std::vector<double> pv(tot);
+            if (P->fp64) HIPCHK(hipMemcpy(pv.data(), P->d_psi.p, tot * 8, hipMemcpyDeviceToHost));
+            else {
+                std::vector<float> f(tot);
+                HIPCHK(hipMemcpy(f.data(), P->d_psi.p, tot * 4, hipMemcpyDeviceToHost));
+                std::copy(f.begin(), f.end(), pv.begin());
+            }
+            for (int k = 0; k < (int)P->user_of[0].size(); ++k) {
+                const int u = P->user_of[0][k];
+                if (u < 0) continue;
+                const double inv = 1.0 / h->w[u];
+                for (int64_t c = 0; c < h->cells; ++c) psi[(size_t)u * h->cells + c] = pv[(size_t)c * al + k] * inv;
+            }
+        }
+        (void)sd;
+        h->plan.reset();  // a one-off plan; forget any cached solve plan's device result
+        h->res_dev = nullptr;
+    } catch (const Fail& f) {
+        return fail(h, f.code, f.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(h, ROM_E_NOMEM, "host allocation failed");
+    }
+    return ROM_OK;
+}
+
+}  // extern "C"
+
+namespace {
+
+bool is_aniso(const rom_handle* h) { return h->scat != ROM_SCAT_ISO; }
+
+// Source iteration for a list of systems; fills stats and phis.
+int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opts& o, bool cache, std::unique_ptr<Plan>& slot,
+                  SolveResult& res)
+{
+    const bool aniso = is_aniso(in[0].h);
+    for (auto& s : in)
+        if (is_aniso(s.h) != aniso) return fail(owner, ROM_E_ARG, "batched problems must all be isotropic or all anisotropic");
+    if (aniso && in.size() > 1 && o.precision == ROM_PREC_FP32) {
+        // every system gets its own contraction launch; nothing else to check
+    }
+    if (!cache || !slot) {
+        slot.reset(new Plan());
+        build_plan(*slot, in, o, aniso, o.max_iter);
+        if (aniso) build_kernel_matrices(*slot, in);
+    }
+    res = run_si(*slot, owner->stream(), o);
+    if (res.error) return fail(owner, ROM_E_DEVICE, "sweep dependency wait timed out");
+    return ROM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rom_source_iterate(rom_handle* h, const rom_si_opts* opts, double* phi, rom_si_stats* stats)
+{
+    if (!h) return ROM_E_ARG;
+    if (h->n == 0) return fail(h, ROM_E_STATE, "set ordinates first");
+    rom_si_opts o;
+    int rc = validate_opts(h, opts, o);
+    if (rc) return rc;
+    try {
+        std::vector<SysInput> in{{h, h->dirs.data(), h->w.data(), h->n, true}};
+        const std::string sig = plan_signature(o, is_aniso(h), 0, 1);
+        const bool reuse = h->plan && h->plan_version == h->version && h->plan_sig == sig;
+        if (!reuse) h->plan.reset();
+        SolveResult res;
+        rc = solve_systems(h, in, o, reuse, h->plan, res);
+        if (rc) return rc;
+        h->plan_version = h->version;
+        h->plan_sig = sig;
+        Plan& P = *h->plan;
+        const SysCtl& sc = res.sc[0];
+        if (phi) download_phi(P, 0, phi);
+        h->res_dev = (const char*)P.d_phi.p + P.sys[0].phi_off * P.esz;
+        h->res_fp64 = P.fp64;
+        if (stats) {
+            stats->iters = sc.iter;
+            stats->final_r = sc.r;
+            stats->status = sc.state == 1 ? ROM_OK : ROM_NOT_CONVERGED;
+            stats->updates = (int64_t)sc.iter * h->cells * h->n;
+            stats->device_ms = res.ms;
+            stats->sweep_ms = res.sweep_ms;
+            stats->sweeps = res.sweeps;
+        }
+        if (sc.state == 3) return fail(h, ROM_E_DIVERGED, "non-finite iterate");
+        return sc.state == 1 ? ROM_OK : ROM_NOT_CONVERGED;
+    } catch (const Fail& f) {
+        h->plan.reset();
+        return fail(h, f.code, f.msg);
+    } catch (const std::bad_alloc&) {
+        h->plan.reset();
+        return fail(h, ROM_E_NOMEM, "host allocation failed");
+    }
+}
+
+int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, double* const* phis, rom_si_stats* stats)
+{
+    if (!hs || k <= 0) return fail(nullptr, ROM_E_ARG, "need at least one handle");
+    rom_handle* h0 = hs[0];
+    if (!h0) return fail(nullptr, ROM_E_ARG, "NULL handle");
+    for (int i = 0; i < k; ++i) {
+        if (!hs[i]) return fail(h0, ROM_E_ARG, "NULL handle in batch");
+        if (hs[i]->n == 0) return fail(h0, ROM_E_STATE, "every handle needs ordinates");
+        if (hs[i]->user_stream != h0->user_stream) return fail(h0, ROM_E_ARG, "handles must share one stream");
+        if (hs[i]->scat == ROM_SCAT_DENSE && k > 1) return fail(h0, ROM_E_UNSUPPORTED, "dense kernels are not batched");
+        for (int j = 0; j < i; ++j)
+            if (hs[j] == hs[i]) return fail(h0, ROM_E_ARG, "a handle appears twice in the batch");
+    }
+    rom_si_opts o;
+    int rc = validate_opts(h0, opts, o);
+    if (rc) return rc;
+    try {
+        std::vector<SysInput> in;
+        for (int i = 0; i < k; ++i) in.push_back({hs[i], hs[i]->dirs.data(), hs[i]->w.data(), hs[i]->n, true});
+        std::unique_ptr<Plan> P;
+        SolveResult res;
+        rc = solve_systems(h0, in, o, false, P, res);
+        if (rc) return rc;
+        int worst = ROM_OK;
+        for (int i = 0; i < k; ++i) {
+            const SysCtl& sc = res.sc[i];
+            if (phis && phis[i]) download_phi(*P, i, phis[i]);
+            if (stats) {
+                stats[i].iters = sc.iter;
+                stats[i].final_r = sc.r;
+                stats[i].status = sc.state == 1 ? ROM_OK : ROM_NOT_CONVERGED;
+                stats[i].updates = (int64_t)sc.iter * hs[i]->cells * hs[i]->n;
+                stats[i].device_ms = res.ms;
+            }
+            if (sc.state == 3) worst = ROM_E_DIVERGED;
+            else if (sc.state != 1 && worst == ROM_OK) worst = ROM_NOT_CONVERGED;
+        }
+        // keep the batch plan alive on the first handle so its device results stay readable
+        h0->plan = std::move(P);
+        h0->plan_version = 0;
+        h0->res_dev = nullptr;
+        return worst;
+    } catch (const Fail& f) {
+        return fail(h0, f.code, f.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(h0, ROM_E_NOMEM, "host allocation failed");
+    }
+}
+
+int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* spec, const rom_si_opts* opts, double* mean,
+                 double* var, rom_ens_stats* stats)
+{
+    if (!h) return ROM_E_ARG;
+    if (t <= 0 || !spec) return fail(h, ROM_E_ARG, "t must be > 0 and spec non-NULL");
+    const int n = ordinate_count(*spec);
+    if (n <= 0) return fail(h, ROM_E_ARG, "bad ordinate spec");
+    if (h->scat == ROM_SCAT_DENSE) return fail(h, ROM_E_STATE, "a dense kernel belongs to one ordinate set");
+    rom_si_opts o;
+    int rc = validate_opts(h, opts, o);
+    if (rc) return rc;
+    try {
+        hipStream_t s = h->stream();
+        HIPCHK(h->ens_mean.alloc(h->cells * 8));
+        HIPCHK(h->ens_m2.alloc(h->cells * 8));
+        HIPCHK(h->ens_var.alloc(h->cells * 8));
+        // batch size: bounded by a device-memory budget for the per-sample buffers
+        const bool aniso = is_aniso(h);
+        const int64_t per_sample = h->cells * (int64_t)(aniso ? (n + 128) * 6 : 0) + h->cells * 8 * 8 +
+                                   (int64_t)h->grid.nx * h->grid.ny / 2 * 4;
+        const int64_t budget = (int64_t)24 << 30;
+        int B = (int)std::max<int64_t>(1, std::min<int64_t>(t, budget / std::max<int64_t>(per_sample, 1)));
+        B = std::min(B, 1024);
+        std::vector<double> dirs((size_t)t * 3 * n), w((size_t)t * n);
+        for (int smp = 0; smp < t; ++smp) {
+            rc = generate_ordinates(*spec, seed, smp, dirs.data() + (size_t)smp * 3 * n, w.data() + (size_t)smp * n);
+            if (rc) return fail(h, rc, "ordinate generation failed");
+        }
+        int done = 0, min_it = 1 << 30, max_it = 0, worst = ROM_OK;
+        int64_t updates = 0;
+        double ms = 0;
+        std::unique_ptr<Plan> P;
+        std::vector<int64_t> offs;
+        DevMem d_offs;
+        while (done < t) {
+            const int b = std::min(B, t - done);
+            std::vector<SysInput> in;
+            for (int k = 0; k < b; ++k)
+                in.push_back({h, dirs.data() + (size_t)(done + k) * 3 * n, w.data() + (size_t)(done + k) * n, n, false});
+            SolveResult res;
+            P.reset();
+            rc = solve_systems(h, in, o, false, P, res);
+            if (rc) return rc;
+            ms += res.ms;
+            offs.assign(b, 0);
+            for (int k = 0; k < b; ++k) {
+                offs[k] = P->sys[k].phi_off;
+                const SysCtl& sc = res.sc[k];
+                min_it = std::min(min_it, sc.iter);
+                max_it = std::max(max_it, sc.iter);
+                updates += (int64_t)sc.iter * h->cells * n;
+                if (sc.state == 3) worst = ROM_E_DIVERGED;
+                else if (sc.state != 1 && worst == ROM_OK) worst = ROM_NOT_CONVERGED;
+            }
+            upload(d_offs, offs);
+            MomentsArgs ma{};
+            ma.phi = P->d_phi.p;
+            ma.phi_offs = d_offs.as<int64_t>();
+            ma.t = b;
+            ma.count = done;
+            ma.cells = h->cells;
+            ma.mean = h->ens_mean.as<double>();
+            ma.m2 = h->ens_m2.as<double>();
+            HIPCHK(launch_moments(ma, P->fp64, s));
+            done += b;
+        }
+        HIPCHK(launch_finish_var(h->ens_m2.as<double>(), h->ens_var.as<double>(), h->cells, t, s));
+        HIPCHK(hipStreamSynchronize(s));
+        if (mean) HIPCHK(hipMemcpy(mean, h->ens_mean.p, h->cells * 8, hipMemcpyDeviceToHost));
+        if (var) HIPCHK(hipMemcpy(var, h->ens_var.p, h->cells * 8, hipMemcpyDeviceToHost));
+        h->plan = std::move(P);
+        h->plan_version = 0;
+        h->res_dev = h->ens_mean.p;
+        h->res_fp64 = true;
+        if (stats) {
+            stats->samples = t;
+            stats->min_iters = min_it;
+            stats->max_iters = max_it;
+            stats->status = worst == ROM_OK ? ROM_OK : ROM_NOT_CONVERGED;
+            stats->updates = updates;
+            stats->device_ms = ms;
+        }
+        if (worst == ROM_E_DIVERGED) return fail(h, ROM_E_DIVERGED, "non-finite iterate in a sample");
+        return worst;
+    } catch (const Fail& f) {
+        return fail(h, f.code, f.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(h, ROM_E_NOMEM, "host allocation failed");
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,84 @@
+// rom_device.h -- data layout shared by the host runtime and the gfx950 kernels of librom.
+//
+// Vocabulary
+//   problem      grid + cross sections + source (+ inflow) of eq. (1.1)-(1.2);
+//   system       one problem with one ordinate set (one ROM sample); it owns a scalar flux, a
+//                source, a convergence state;
+//   group        L consecutive lanes of a wavefront holding up to L ordinates of one quadrant of
+//                one system (L = 16, 32 or 64; a wavefront holds G = 64/L groups, all from one
+//                problem and one quadrant, so they march the same cell order);
+//   wave-stream  the 64 lanes of such a wavefront together with its quadrant: it sweeps the
+//                whole grid, strip by strip (TY rows each), chunk by chunk (TX columns each);
+//   strip task   (wave-stream, strip): the unit a persistent wavefront claims from the ticket
+//                list.  Tickets are ordered by strip index first, so the producer of every strip
+//                edge holds an earlier ticket than its consumer.
+//
+// Angular fluxes are carried scaled by their quadrature weight (psi' = w psi), so a group's
+// scalar-flux contribution is the plain lane sum and the anisotropic contraction multiplies by
+// P instead of W = w P (eq. (3.4)).
+#pragma once
+#include <stdint.h>
+
+namespace rom {
+
+constexpr int kWave = 64;
+constexpr int kMaxGroups = 4;
+
+struct ProblemDev {
+    int32_t nx, ny;
+    int32_t nchunks;      // ceil(nx / TX)
+    int32_t nstrips;      // ceil(ny / TY)
+    int64_t field_off;    // offset of sigma_t / sigma_s / q in the field pools (elements)
+};
+
+struct WaveStreamDev {
+    int32_t prob;               // problem index
+    int32_t quad;               // 0: c>=0,s>=0  1: c<0,s>=0  2: c<0,s<0  3: c>=0,s<0
+    int32_t L;                  // lanes per group (16, 32, 64)
+    int32_t prog_off;           // first progress counter (one per strip)
+    int64_t edge_off;           // strip-edge buffer [nstrips][nx][64] (elements of T)
+    int64_t xin_off;            // inflow on the entry x-face [ny][64] in sweep order, -1 = vacuum
+    int64_t yin_off;            // inflow on the entry y-face [nx][64] in sweep order, -1 = vacuum
+    int32_t sys[kMaxGroups];    // system of each group (-1: empty group)
+    int32_t slot[kMaxGroups];   // partial-flux slot of each group (-1: empty group)
+};
+
+struct LaneDev {                // per (wave-stream, lane); padded lanes have w = a = b = 0
+    double a, b, w;             // |c|/dx, |s|/dy, quadrature weight
+    int32_t ord;                // internal (padded, quadrant-grouped) ordinate index in its system
+    int32_t pad;
+};
+
+struct SystemDev {
+    int32_t prob;
+    int32_t npad;               // internal padded ordinate count (anisotropic layout [cells][npad])
+    int32_t nslots;             // partial slots summed by the combine step, in this order
+    int32_t slot_first;         // index into the slot-order list
+    int64_t phi_off;            // scalar flux [cells] (elements of T)
+    int64_t src_off;            // isotropic source [cells] (elements of T)
+    int64_t ang_off;            // anisotropic source / angular flux [cells][npad] (elements)
+};
+
+// Per-system convergence state, written only by the combine step.
+struct SysCtl {
+    unsigned long long dmax_bits;   // max |phi^k - phi^{k-1}| of the running iteration (FP64 bits)
+    unsigned long long pmax_bits;   // max |phi^k|
+    int32_t iter;                   // completed iterations
+    int32_t state;                  // 0 running, 1 converged, 2 stopped at max_iter, 3 diverged
+    int32_t grow;                   // consecutive iterations with a growing change
+    int32_t pad;
+    double r;                       // last relative change
+    double r_prev;
+};
+
+struct Ctl {
+    int32_t ticket;         // next strip ticket
+    int32_t epoch;          // sweep generation, tags the progress counters
+    int32_t blocks_done;    // combine blocks finished in this iteration
+    int32_t active;         // systems still running after the last combine step
+    int32_t error;          // 1: a dependency wait timed out
+    int32_t launches;       // sweeps launched
+    int32_t pad[2];
+};
+
+}  // namespace rom

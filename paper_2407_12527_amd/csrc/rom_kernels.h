@@ -1,0 +1,88 @@
+// rom_kernels.h -- kernel arguments and launchers of librom (host and device side).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "rom_device.h"
+
+namespace rom {
+
+struct SweepArgs {
+    const ProblemDev* probs;
+    const WaveStreamDev* ws;
+    const LaneDev* lanes;      // [nws][64]
+    const SystemDev* sys;
+    const int2* tickets;       // (wave-stream, strip), strip-major
+    int32_t ntickets;
+    int32_t spin_limit;        // polls before a dependency wait gives up
+    int32_t mode_all;          // 1: sweep every wave-stream regardless of convergence state
+    int32_t pad;
+    const void* sigma_t;       // field pool (T)
+    const void* src;           // isotropic source pool (T)
+    const void* ang_src;       // per-ordinate source pool [cells][npad] (T)
+    void* psi_out;             // angular-flux output pool [cells][npad] (T or BF16)
+    void* part;                // partial scalar-flux pool (T)
+    const int64_t* slot_off;   // partial slot -> offset in part
+    void* edge;                // strip-edge pool (T)
+    const void* inflow;        // boundary inflow pool (T)
+    long long* prog;           // strip progress counters
+    Ctl* ctl;
+    SysCtl* sysctl;
+};
+
+struct CombineArgs {
+    const SystemDev* sys;
+    const ProblemDev* probs;
+    const int32_t* slot_order;
+    const int64_t* slot_off;
+    const int2* blocks;        // (system, first cell) per block
+    int32_t cells_per_block;
+    int32_t nsys;
+    int32_t mode;              // 0: source-iteration step, 1: plain sum (single sweep)
+    int32_t max_iter;
+    double tol;
+    const void* part;
+    void* phi;
+    void* src;
+    const void* sigma_s;
+    const void* q;
+    SysCtl* sysctl;
+    Ctl* ctl;
+    double* rhist;             // optional [nsys][max_iter] relative-change history
+};
+
+struct MomentsArgs {
+    const void* phi;           // pool holding the per-sample fluxes
+    const int64_t* phi_offs;   // [t] offsets of the samples of this batch
+    int32_t t;                 // samples in this batch
+    int32_t pad;
+    int64_t count;             // samples already accumulated (0: first batch)
+    int64_t cells;
+    double* mean;
+    double* m2;
+};
+
+struct ContractArgs {
+    const void* a;             // Psi' [M][K] (BF16, FP32 or FP64)
+    const void* bt;            // P^T [N][K]
+    const void* sigma_s;       // [M]
+    const void* q;             // [M]
+    void* out;                 // S [M][N]
+    int32_t M, N, K;
+    int32_t sys_index;
+    const SysCtl* sysctl;      // skip when that system has stopped (NULL: always run)
+};
+
+hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty, bool dd, bool ang, int psi,
+                        hipStream_t s);
+bool sweep_tile_supported(int tx, int ty);
+hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s);
+hipError_t launch_sweep_prologue(Ctl* ctl, hipStream_t s);
+hipError_t launch_reset_systems(SysCtl* sc, int nsys, Ctl* ctl, hipStream_t s);
+hipError_t launch_fill(void* p, int64_t n, bool fp64, double v, hipStream_t s);
+hipError_t launch_moments(const MomentsArgs& a, bool fp64, hipStream_t s);
+hipError_t launch_finish_var(const double* m2, double* var, int64_t cells, int64_t t, hipStream_t s);
+hipError_t launch_contract(const ContractArgs& a, int kind, hipStream_t s);  // 0 bf16 MFMA, 1 fp32, 2 fp64
+hipError_t launch_cast_bf16(const float* in, void* out, int64_t n, hipStream_t s);
+
+}  // namespace rom

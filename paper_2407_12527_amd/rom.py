@@ -1,0 +1,354 @@
+"""ctypes binding of librom (include/rom.h): same names as the C ABI, argument marshalling only.
+
+Every compute step runs in librom's gfx950 kernels.  The raw functions ``rom_*`` take and return
+exactly what the C functions do (numpy arrays are passed as host pointers); ``Handle`` wraps a
+``rom_handle*`` with numpy-friendly methods and raises ``RomError`` on negative status codes.
+PyTorch is used only to hand librom a HIP stream (``Handle.use_torch_stream``) and to view
+device-resident results (``Handle.phi_device_tensor``).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+__all__ = [
+    "ROM_OK", "ROM_NOT_CONVERGED", "ROM_E_ARG", "ROM_E_DOMAIN", "ROM_E_STATE", "ROM_E_NOMEM", "ROM_E_DEVICE",
+    "ROM_E_DIVERGED", "ROM_E_UNSUPPORTED", "ROM_SCHEME_STEP", "ROM_SCHEME_DD", "ROM_SCAT_ISO", "ROM_SCAT_LINEAR",
+    "ROM_SCAT_HG", "ROM_SCAT_DENSE", "ROM_ORD_STRATIFIED", "ROM_ORD_IID_SPHERE", "ROM_ORD_UNIFORM2D",
+    "ROM_ORD_GAUSS2D", "ROM_PREC_FP32", "ROM_PREC_FP64", "ROM_FACE_LEFT", "ROM_FACE_RIGHT", "ROM_FACE_BOTTOM",
+    "ROM_FACE_TOP", "rom_grid", "rom_inflow", "rom_ord_spec", "rom_si_opts", "rom_si_stats", "rom_ens_stats",
+    "RomError", "Handle", "lib", "library_path", "EXPORTS", "generate_ordinates", "ordinate_count",
+    "solve_batch", "si_opts", "rom_create", "rom_destroy", "rom_set_stream", "rom_set_ordinates",
+    "rom_set_inflow_angular", "rom_set_scattering", "rom_sweep", "rom_source_iterate", "rom_ensemble",
+    "rom_solve_batch", "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
+    "rom_last_error", "rom_version",
+]
+
+ROM_OK, ROM_NOT_CONVERGED = 0, 1
+ROM_E_ARG, ROM_E_DOMAIN, ROM_E_STATE, ROM_E_NOMEM, ROM_E_DEVICE, ROM_E_DIVERGED, ROM_E_UNSUPPORTED = \
+    -1, -2, -3, -4, -5, -6, -7
+ROM_SCHEME_STEP, ROM_SCHEME_DD = 0, 1
+ROM_SCAT_ISO, ROM_SCAT_LINEAR, ROM_SCAT_HG, ROM_SCAT_DENSE = 0, 1, 2, 3
+ROM_ORD_STRATIFIED, ROM_ORD_IID_SPHERE, ROM_ORD_UNIFORM2D, ROM_ORD_GAUSS2D = 0, 1, 2, 3
+ROM_PREC_FP32, ROM_PREC_FP64 = 0, 1
+ROM_FACE_LEFT, ROM_FACE_RIGHT, ROM_FACE_BOTTOM, ROM_FACE_TOP = 0, 1, 2, 3
+
+# every function declared in include/rom.h
+EXPORTS = ("rom_create", "rom_destroy", "rom_set_stream", "rom_set_ordinates", "rom_set_inflow_angular",
+           "rom_set_scattering", "rom_sweep", "rom_source_iterate", "rom_ensemble", "rom_solve_batch",
+           "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
+           "rom_last_error", "rom_version")
+
+
+class rom_grid(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("x0", C.c_double), ("x1", C.c_double),
+                ("y0", C.c_double), ("y1", C.c_double)]
+
+
+class rom_inflow(C.Structure):
+    _fields_ = [("left", C.c_void_p), ("right", C.c_void_p), ("bottom", C.c_void_p), ("top", C.c_void_p)]
+
+
+class rom_ord_spec(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("p1", C.c_int32), ("p2", C.c_int32)]
+
+
+class rom_si_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32), ("scheme", C.c_int32),
+                ("iters_per_check", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
+                ("contract_split", C.c_int32), ("timing", C.c_int32), ("reserved", C.c_int32 * 3)]
+
+
+class rom_si_stats(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("final_r", C.c_double), ("updates", C.c_int64),
+                ("device_ms", C.c_double), ("sweep_ms", C.c_double), ("sweeps", C.c_int32), ("pad", C.c_int32)]
+
+
+class rom_ens_stats(C.Structure):
+    _fields_ = [("samples", C.c_int32), ("min_iters", C.c_int32), ("max_iters", C.c_int32), ("status", C.c_int32),
+                ("updates", C.c_int64), ("device_ms", C.c_double)]
+
+
+def library_path() -> str:
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "librom.so")
+
+
+_lib = None
+
+
+def lib():
+    """Load librom.so (built in-tree by ``build.py``).  Raises if it is missing: there is no
+    fallback path."""
+    global _lib
+    if _lib is None:
+        path = library_path()
+        if not os.path.exists(path):
+            raise RuntimeError(f"librom.so not built ({path}); run `python -m paper_2407_12527_amd.build`")
+        L = C.CDLL(path)
+        P = C.c_void_p
+        PH = C.POINTER(C.c_void_p)
+        L.rom_create.argtypes = [C.POINTER(rom_grid), P, P, P, C.POINTER(rom_inflow), PH]
+        L.rom_destroy.argtypes = [P]
+        L.rom_destroy.restype = None
+        L.rom_set_stream.argtypes = [P, P]
+        L.rom_set_ordinates.argtypes = [P, C.c_int32, P, P]
+        L.rom_set_inflow_angular.argtypes = [P, C.c_int32, P]
+        L.rom_set_scattering.argtypes = [P, C.c_int32, C.c_double, P]
+        L.rom_sweep.argtypes = [P, P, C.c_int32, P, P, C.POINTER(rom_si_opts)]
+        L.rom_source_iterate.argtypes = [P, C.POINTER(rom_si_opts), P, C.POINTER(rom_si_stats)]
+        L.rom_ensemble.argtypes = [P, C.c_int32, C.c_uint64, C.POINTER(rom_ord_spec), C.POINTER(rom_si_opts), P, P,
+                                   C.POINTER(rom_ens_stats)]
+        L.rom_solve_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(rom_si_opts),
+                                      C.POINTER(C.c_void_p), C.POINTER(rom_si_stats)]
+        L.rom_phi_device.argtypes = [P, C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]
+        L.rom_generate_ordinates.argtypes = [C.POINTER(rom_ord_spec), C.c_uint64, C.c_int64, P, P]
+        L.rom_ordinate_count.argtypes = [C.POINTER(rom_ord_spec)]
+        L.rom_ordinate_count.restype = C.c_int32
+        L.rom_status_string.argtypes = [C.c_int]
+        L.rom_status_string.restype = C.c_char_p
+        L.rom_last_error.argtypes = [P]
+        L.rom_last_error.restype = C.c_char_p
+        L.rom_version.restype = C.c_char_p
+        _lib = L
+    return _lib
+
+
+# ------------------------------------------------------------------ raw functions (same names)
+def rom_create(grid, sigma_t, sigma_s, q, inflow, out):
+    return lib().rom_create(grid, sigma_t, sigma_s, q, inflow, out)
+
+
+def rom_destroy(h):
+    return lib().rom_destroy(h)
+
+
+def rom_set_stream(h, stream):
+    return lib().rom_set_stream(h, stream)
+
+
+def rom_set_ordinates(h, n, dirs, w):
+    return lib().rom_set_ordinates(h, n, dirs, w)
+
+
+def rom_set_inflow_angular(h, face, vals):
+    return lib().rom_set_inflow_angular(h, face, vals)
+
+
+def rom_set_scattering(h, kind, g, P):
+    return lib().rom_set_scattering(h, kind, g, P)
+
+
+def rom_sweep(h, src, src_per_ordinate, phi, psi, opts):
+    return lib().rom_sweep(h, src, src_per_ordinate, phi, psi, opts)
+
+
+def rom_source_iterate(h, opts, phi, stats):
+    return lib().rom_source_iterate(h, opts, phi, stats)
+
+
+def rom_ensemble(h, t, seed, spec, opts, mean, var, stats):
+    return lib().rom_ensemble(h, t, seed, spec, opts, mean, var, stats)
+
+
+def rom_solve_batch(hs, k, opts, phis, stats):
+    return lib().rom_solve_batch(hs, k, opts, phis, stats)
+
+
+def rom_phi_device(h, dev, is_fp64):
+    return lib().rom_phi_device(h, dev, is_fp64)
+
+
+def rom_generate_ordinates(spec, seed, sample, dirs, w):
+    return lib().rom_generate_ordinates(spec, seed, sample, dirs, w)
+
+
+def rom_ordinate_count(spec):
+    return lib().rom_ordinate_count(spec)
+
+
+def rom_status_string(st):
+    return lib().rom_status_string(st)
+
+
+def rom_last_error(h):
+    return lib().rom_last_error(h)
+
+
+def rom_version():
+    return lib().rom_version()
+
+
+# ------------------------------------------------------------------ helpers
+class RomError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{lib().rom_status_string(status).decode()} ({status}): {msg}")
+        self.status = status
+
+
+def _f64(a, n=None):
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    if n is not None and a.size != n:
+        raise ValueError(f"expected {n} values, got {a.size}")
+    return a
+
+
+def _ptr(a):
+    return None if a is None else C.c_void_p(a.ctypes.data)
+
+
+def _check(st, h=None):
+    if st < 0:
+        raise RomError(st, (lib().rom_last_error(h) or b"").decode())
+    return st
+
+
+def si_opts(tol=1e-6, max_iter=1000, precision=ROM_PREC_FP32, scheme=ROM_SCHEME_STEP, iters_per_check=0,
+            tile=(0, 0), contract_split=0, timing=0) -> rom_si_opts:
+    o = rom_si_opts()
+    o.tol = tol
+    o.max_iter = max_iter
+    o.precision = precision
+    o.scheme = scheme
+    o.iters_per_check = iters_per_check
+    o.tile_x, o.tile_y = tile
+    o.contract_split = contract_split
+    o.timing = timing
+    return o
+
+
+def ordinate_count(kind, p1, p2=0) -> int:
+    return int(lib().rom_ordinate_count(C.byref(rom_ord_spec(kind, p1, p2))))
+
+
+def generate_ordinates(kind, p1, p2=0, seed=0, sample=0):
+    """Ordinate set of one sample, as librom generates it (host code, no device work)."""
+    spec = rom_ord_spec(kind, p1, p2)
+    n = lib().rom_ordinate_count(C.byref(spec))
+    if n <= 0:
+        raise RomError(ROM_E_ARG, "bad ordinate spec")
+    dirs = np.empty((n, 3))
+    w = np.empty(n)
+    _check(lib().rom_generate_ordinates(C.byref(spec), seed, sample, _ptr(dirs), _ptr(w)))
+    return dirs, w
+
+
+class Handle:
+    """Owns one ``rom_handle*`` (a problem on the current HIP device)."""
+
+    def __init__(self, nx, ny, sigma_t, sigma_s, q, box=(0.0, 1.0, 0.0, 1.0), inflow=None):
+        cells = nx * ny
+        self.nx, self.ny, self.cells = int(nx), int(ny), cells
+        self._keep = []
+        st, ss, qq = _f64(sigma_t, cells), _f64(sigma_s, cells), _f64(q, cells)
+        g = rom_grid(nx, ny, *box)
+        fin = None
+        if inflow:
+            fin = rom_inflow()
+            for k in ("left", "right", "bottom", "top"):
+                v = inflow.get(k)
+                if v is not None:
+                    v = _f64(v, ny if k in ("left", "right") else nx)
+                    self._keep.append(v)
+                    setattr(fin, k, v.ctypes.data)
+        h = C.c_void_p()
+        _check(lib().rom_create(C.byref(g), _ptr(st), _ptr(ss), _ptr(qq), C.byref(fin) if fin else None, C.byref(h)))
+        self.h = h
+        self.n = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().rom_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream_ptr):
+        _check(lib().rom_set_stream(self.h, C.c_void_p(stream_ptr)), self.h)
+
+    def use_torch_stream(self, stream=None):
+        import torch
+        s = stream if stream is not None else torch.cuda.current_stream()
+        self.set_stream(s.cuda_stream)
+
+    def set_ordinates(self, dirs, w):
+        dirs = _f64(dirs)
+        w = _f64(w)
+        self.n = int(w.size)
+        _check(lib().rom_set_ordinates(self.h, self.n, _ptr(dirs), _ptr(w)), self.h)
+
+    def set_inflow_angular(self, face, vals):
+        v = None if vals is None else _f64(vals)
+        _check(lib().rom_set_inflow_angular(self.h, face, _ptr(v)), self.h)
+
+    def set_scattering(self, kind, g=0.0, P=None):
+        p = None if P is None else _f64(P)
+        _check(lib().rom_set_scattering(self.h, kind, g, _ptr(p)), self.h)
+
+    def sweep(self, src, opts=None, want_psi=False):
+        src = _f64(src)
+        per = 1 if src.size != self.cells else 0
+        phi = np.empty(self.cells)
+        psi = np.empty((self.n, self.cells)) if want_psi else None
+        _check(lib().rom_sweep(self.h, _ptr(src), per, _ptr(phi), _ptr(psi), C.byref(opts) if opts else None), self.h)
+        return (phi, psi) if want_psi else phi
+
+    def source_iterate(self, opts=None, download=True):
+        phi = np.empty(self.cells) if download else None
+        st = rom_si_stats()
+        rc = _check(lib().rom_source_iterate(self.h, C.byref(opts) if opts else None, _ptr(phi), C.byref(st)), self.h)
+        return phi, st, rc
+
+    def ensemble(self, t, seed, kind, p1, p2=0, opts=None, download=True):
+        mean = np.empty(self.cells) if download else None
+        var = np.empty(self.cells) if download else None
+        st = rom_ens_stats()
+        spec = rom_ord_spec(kind, p1, p2)
+        rc = _check(lib().rom_ensemble(self.h, t, seed, C.byref(spec), C.byref(opts) if opts else None, _ptr(mean),
+                                       _ptr(var), C.byref(st)), self.h)
+        return mean, var, st, rc
+
+    def phi_device(self):
+        dev = C.c_void_p()
+        f64 = C.c_int32()
+        _check(lib().rom_phi_device(self.h, C.byref(dev), C.byref(f64)), self.h)
+        return dev.value, bool(f64.value)
+
+    def phi_device_tensor(self):
+        """Copy of the device-resident result as a torch tensor on the current device."""
+        import torch
+        ptr, f64 = self.phi_device()
+        dt = torch.float64 if f64 else torch.float32
+        out = torch.empty(self.cells, dtype=dt, device="cuda")
+        _hip_memcpy_d2d(out.data_ptr(), ptr, self.cells * (8 if f64 else 4))
+        return out
+
+
+def solve_batch(handles, opts=None):
+    k = len(handles)
+    hs = (C.c_void_p * k)(*[h.h for h in handles])
+    outs = [np.empty(h.cells) for h in handles]
+    ps = (C.c_void_p * k)(*[o.ctypes.data for o in outs])
+    stats = (rom_si_stats * k)()
+    rc = lib().rom_solve_batch(hs, k, C.byref(opts) if opts else None, ps, stats)
+    if rc < 0:
+        raise RomError(rc, (lib().rom_last_error(handles[0].h) or b"").decode())
+    return outs, list(stats), rc
+
+
+_hip = None
+
+
+def _hip_memcpy_d2d(dst, src, nbytes):
+    global _hip
+    if _hip is None:
+        _hip = C.CDLL("libamdhip64.so")
+        _hip.hipMemcpy.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t, C.c_int]
+    rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), nbytes, 3)  # hipMemcpyDeviceToDevice
+    if rc != 0:
+        raise RomError(ROM_E_DEVICE, f"hipMemcpy failed ({rc})")

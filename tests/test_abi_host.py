@@ -1,0 +1,175 @@
+"""Host-side checks of the C-ABI library (no GPU needed): it loads, exports every entry point
+that include/rom.h declares, generates ordinate sets bit-identical to the oracle's, and rejects
+invalid input with the documented status codes before touching a device."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def R():
+    from paper_2407_12527_amd import rom
+    rom.lib()
+    return rom
+
+
+def _declared_functions():
+    text = open(os.path.join(ROOT, "include", "rom.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(rom_[a-z_0-9]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol(R):
+    names = _declared_functions()
+    assert len(names) >= 16
+    L = R.lib()
+    for n in names:
+        assert hasattr(L, n), n
+    assert set(names) == set(R.EXPORTS)
+    assert R.rom_version().startswith(b"librom")
+
+
+def test_status_strings(R):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7):
+        assert len(R.rom_status_string(code)) > 0
+    assert R.rom_status_string(99) == b"unknown status"
+
+
+@pytest.mark.parametrize("kind,p1,p2,count", [(0, 8, 8, 256), (0, 4, 8, 128), (0, 16, 16, 1024), (1, 32, 0, 32),
+                                              (2, 20, 0, 1600), (3, 20, 0, 840), (3, 200, 0, 80400), (0, 0, 3, -1),
+                                              (9, 1, 1, -1)])
+def test_ordinate_count(R, kind, p1, p2, count):
+    assert R.rom_ordinate_count(C.byref(R.rom_ord_spec(kind, p1, p2))) == count
+
+
+@pytest.mark.parametrize("kind,p1,p2", [(0, 8, 8), (0, 4, 8), (0, 16, 16), (0, 1, 7), (0, 3, 5), (1, 32, 0), (1, 5, 0)])
+@pytest.mark.parametrize("seed,sample", [(0, 0), (0, 63), (12345, 7), (2**63 + 5, 1)])
+def test_random_ordinates_bit_identical_to_oracle(R, orc, kind, p1, p2, seed, sample):
+    """The library and the oracle implement the same published generator and draw formulas
+    independently; their ordinate sets must agree bit for bit."""
+    d_lib, w_lib = R.generate_ordinates(kind, p1, p2, seed=seed, sample=sample)
+    okind = orc.ORD_STRATIFIED if kind == 0 else orc.ORD_IID_SPHERE
+    d_or, w_or = orc.generate(okind, p1, p2, seed=seed, sample=sample)
+    assert np.array_equal(d_lib.view(np.uint64), d_or.view(np.uint64))
+    assert np.array_equal(w_lib.view(np.uint64), w_or.view(np.uint64))
+
+
+@pytest.mark.parametrize("kind,N", [(2, 3), (2, 20), (3, 5), (3, 20), (3, 200)])
+def test_quadratures_match_oracle(R, orc, kind, N):
+    d_lib, w_lib = R.generate_ordinates(kind, N)
+    d_or, w_or = orc.generate(kind, N)
+    np.testing.assert_allclose(d_lib, d_or, rtol=0, atol=1e-15)
+    np.testing.assert_allclose(w_lib, w_or, rtol=2e-14, atol=0)
+
+
+def _grid(R, nx=4, ny=3):
+    return R.rom_grid(nx, ny, 0.0, 1.0, 0.0, 1.0)
+
+
+def _create(R, st, ss, q, nx=4, ny=3, inflow=None, grid=None):
+    h = C.c_void_p()
+    a = [np.ascontiguousarray(v, dtype=np.float64) for v in (st, ss, q)]
+    rc = R.rom_create(C.byref(grid or _grid(R, nx, ny)), a[0].ctypes.data, a[1].ctypes.data, a[2].ctypes.data,
+                      C.byref(inflow) if inflow else None, C.byref(h))
+    return rc, h
+
+
+@pytest.mark.parametrize("case,code", [
+    ("sigma_t_zero", -2), ("sigma_s_neg", -2), ("sigma_s_ge_sigma_t", -2), ("q_neg", -2), ("nan", -2),
+    ("nx_zero", -1), ("box", -1), ("inflow_neg", -2)])
+def test_create_rejects_bad_input(R, case, code):
+    cells = 12
+    st, ss, q = np.ones(cells), np.full(cells, 0.5), np.ones(cells)
+    grid = None
+    inflow = None
+    keep = None
+    if case == "sigma_t_zero":
+        st[3] = 0.0
+    elif case == "sigma_s_neg":
+        ss[0] = -1e-3
+    elif case == "sigma_s_ge_sigma_t":
+        ss[5] = 1.0
+    elif case == "q_neg":
+        q[2] = -1.0
+    elif case == "nan":
+        q[1] = np.nan
+    elif case == "nx_zero":
+        grid = R.rom_grid(0, 3, 0.0, 1.0, 0.0, 1.0)
+    elif case == "box":
+        grid = R.rom_grid(4, 3, 1.0, 0.0, 0.0, 1.0)
+    elif case == "inflow_neg":
+        keep = np.array([1.0, -1.0, 0.0])
+        inflow = R.rom_inflow(keep.ctypes.data, None, None, None)
+    rc, h = _create(R, st, ss, q, grid=grid, inflow=inflow)
+    assert rc == code
+    assert not h.value
+    assert len(R.rom_last_error(None)) > 0
+
+
+def test_null_arguments(R):
+    h = C.c_void_p()
+    assert R.rom_create(None, None, None, None, None, C.byref(h)) == -1
+    assert R.rom_set_ordinates(None, 1, None, None) == -1
+    assert R.rom_source_iterate(None, None, None, None) == -1
+    assert R.rom_generate_ordinates(None, 0, 0, None, None) == -1
+    R.rom_destroy(None)
+
+
+def test_handle_validation_without_device(R):
+    """Handles are validated and built on the host; ordinate, inflow and scattering errors and
+    call-order errors come back before any device work."""
+    cells = 12
+    rc, h = _create(R, np.ones(cells), np.full(cells, 0.5), np.ones(cells))
+    assert rc == 0 and h.value
+    try:
+        # solve before ordinates
+        assert R.rom_source_iterate(h, None, None, None) == R.ROM_E_STATE
+        assert R.rom_set_inflow_angular(h, 0, None) == R.ROM_E_STATE
+        assert R.rom_set_scattering(h, R.ROM_SCAT_DENSE, 0.0, None) == R.ROM_E_STATE
+        d = np.array([[0.6, 0.8, 0.0], [-0.6, -0.8, 0.0]])
+        w = np.array([0.5, 0.5])
+        assert R.rom_set_ordinates(h, 2, d.ctypes.data, w.ctypes.data) == 0
+        bad = d.copy()
+        bad[0, 0] = 0.7
+        assert R.rom_set_ordinates(h, 2, bad.ctypes.data, w.ctypes.data) == R.ROM_E_DOMAIN
+        w2 = np.array([0.5, 0.4])
+        assert R.rom_set_ordinates(h, 2, d.ctypes.data, w2.ctypes.data) == R.ROM_E_DOMAIN
+        w3 = np.array([1.0, 0.0])
+        assert R.rom_set_ordinates(h, 2, d.ctypes.data, w3.ctypes.data) == R.ROM_E_DOMAIN
+        assert R.rom_set_ordinates(h, 0, d.ctypes.data, w.ctypes.data) == R.ROM_E_ARG
+        assert R.rom_set_scattering(h, 7, 0.0, None) == R.ROM_E_ARG
+        assert R.rom_set_scattering(h, R.ROM_SCAT_HG, 1.0, None) == R.ROM_E_DOMAIN
+        assert R.rom_set_scattering(h, R.ROM_SCAT_HG, 0.8, None) == 0
+        P = np.array([[1.0, -0.5], [0.2, 1.0]])
+        assert R.rom_set_scattering(h, R.ROM_SCAT_DENSE, 0.0, P.ctypes.data) == R.ROM_E_DOMAIN
+        ang = -np.ones(2 * 3)
+        assert R.rom_set_inflow_angular(h, R.ROM_FACE_LEFT, ang.ctypes.data) == R.ROM_E_DOMAIN
+        assert R.rom_set_inflow_angular(h, 9, None) == R.ROM_E_ARG
+        o = R.si_opts(tile=(7, 7))
+        assert R.rom_source_iterate(h, C.byref(o), None, None) == R.ROM_E_ARG
+        o = R.si_opts(precision=5)
+        assert R.rom_source_iterate(h, C.byref(o), None, None) == R.ROM_E_ARG
+        assert R.rom_ensemble(h, 0, 0, C.byref(R.rom_ord_spec(0, 1, 1)), None, None, None, None) == R.ROM_E_ARG
+        assert R.rom_ensemble(h, 2, 0, C.byref(R.rom_ord_spec(0, 0, 1)), None, None, None, None) == R.ROM_E_ARG
+        dev, f = C.c_void_p(), C.c_int32()
+        assert R.rom_phi_device(h, C.byref(dev), C.byref(f)) == R.ROM_E_STATE
+        assert len(R.rom_last_error(h)) > 0
+    finally:
+        R.rom_destroy(h)
+
+
+def test_batch_argument_checks(R):
+    cells = 12
+    rc, h = _create(R, np.ones(cells), np.full(cells, 0.5), np.ones(cells))
+    assert rc == 0
+    try:
+        hs = (C.c_void_p * 2)(h.value, h.value)
+        assert R.rom_solve_batch(hs, 0, None, None, None) == R.ROM_E_ARG
+        assert R.rom_solve_batch(hs, 2, None, None, None) == R.ROM_E_STATE  # no ordinates yet
+    finally:
+        R.rom_destroy(h)
