@@ -247,12 +247,13 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs A)
                     }
                 }
                 xl[r] = xf;
-                if (PSI == 1) {
+                // lanes of empty groups alias ordinate 0 of system sys[0]: they never store
+                if (PSI == 1 && gslot >= 0) {
                     T* __restrict__ po = (T*)A.psi_out + SD.ang_off + ld.ord;
 #pragma unroll
                     for (int i = 0; i < TX; ++i)
                         if (i < cols) po[(int64_t)cidx[i] * npad] = acc[i];
-                } else if (PSI == 2) {
+                } else if (PSI == 2 && gslot >= 0) {
                     __hip_bfloat16* __restrict__ po = (__hip_bfloat16*)A.psi_out + SD.ang_off + ld.ord;
 #pragma unroll
                     for (int i = 0; i < TX; ++i)
