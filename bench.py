@@ -95,7 +95,7 @@ def main():
     n = wl.n_ord[0]
     fp64 = wl.precision == "fp64"
     prec = R.ROM_PREC_FP64 if fp64 else R.ROM_PREC_FP32
-    opts = R.si_opts(tol=wl.tol, max_iter=wl.max_iter, precision=prec, timing=1)
+    opts = R.si_opts(tol=wl.tol, max_iter=wl.max_iter, precision=prec)
     if wl.ord_kind == "stratified":
         m = n // 4
         nz = max(d for d in range(1, int(m ** 0.5) + 1) if m % d == 0)

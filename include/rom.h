@@ -103,8 +103,7 @@ typedef struct {
     int32_t iters_per_check;  /* iterations captured per graph replay between host checks; 0 -> auto */
     int32_t tile_x, tile_y;   /* sweep chunk / strip size in cells; 0 -> autotuned */
     int32_t contract_split;   /* reserved for a split-BF16 contraction; must be 0 */
-    int32_t timing;           /* 1: time every sweep launch with HIP events (stats.sweep_ms) */
-    int32_t reserved[3];
+    int32_t reserved[4];
 } rom_si_opts;
 
 typedef struct {
@@ -113,8 +112,9 @@ typedef struct {
     double final_r;        /* last relative change (largest over systems) */
     int64_t updates;       /* cell x ordinate upwind updates performed */
     double device_ms;      /* device time of the solve, from events on the handle's stream */
-    double sweep_ms;       /* with opts.timing: summed duration of the sweep launches */
-    int32_t sweeps;        /* with opts.timing: sweep launches timed */
+    double sweep_ms;       /* summed duration of the sweep launches that did work, first wave
+                              start to last wave end, from the device real-time clock */
+    int32_t sweeps;        /* sweep launches that did work */
     int32_t pad;
 } rom_si_stats;
 

@@ -171,25 +171,22 @@ struct Plan {
     std::vector<int> sys_n;                 // per system: real ordinate count
     std::vector<const double*> sys_w;       // per system: caller weights
     std::vector<int> npad_al;               // per system: padded stride of the anisotropic layout
-    int cells_per_block = 4096;
+    int cells_per_block = 1024;
 
     DevMem d_probs, d_sys, d_ws, d_lanes, d_tickets, d_slot_off, d_slot_order, d_cblocks;
     DevMem d_st, d_ss, d_q, d_src, d_phi, d_part, d_edge, d_inflow, d_prog, d_ctl, d_sysctl, d_rhist;
-    DevMem d_ang, d_psi, d_Pt;
+    DevMem d_ang, d_psi, d_Pt, d_uflags;
     std::vector<int64_t> pt_off;  // per system offset into d_Pt (elements)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_iters = 0;
-    int graph_timing = 0;
     double graph_tol = 0.0;
     hipStream_t graph_stream = nullptr;
-    std::vector<hipEvent_t> ev;  // with timing: a start/stop pair around every captured sweep
 
     ~Plan()
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
-        for (auto e : ev) (void)hipEventDestroy(e);
     }
 
     SweepArgs sweep_args(int mode_all, int psi_mode) const
@@ -209,6 +206,7 @@ struct Plan {
         a.psi_out = d_psi.p;
         a.part = d_part.p;
         a.slot_off = d_slot_off.as<int64_t>();
+        a.uflags = d_uflags.as<int32_t>();
         a.edge = d_edge.p;
         a.inflow = d_inflow.p;
         a.prog = d_prog.as<long long>();
@@ -260,6 +258,20 @@ int device_cus()
             cus = 256;
     }
     return cus;
+}
+
+// Frequency of the device real-time clock read by wall_clock64(), in kHz (ticks per ms).
+double wallclock_khz()
+{
+    static double khz = 0.0;
+    if (khz == 0.0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
+            khz = v;
+        else
+            khz = 100000.0;
+    }
+    return khz;
 }
 
 void choose_tiles(const rom_si_opts& o, const std::vector<SysInput>& in, bool fp64, int& tx, int& ty)
@@ -324,6 +336,40 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         field_off[p] = fsum;
         fsum += h->cells;
         P.probs.push_back(pd);
+    }
+
+    // row-uniformity masks: bit r of (quadrant, strip, chunk) is set when sigma_t takes a single
+    // value on the chunk's row r, so the sweep can take one reciprocal for the whole row
+    std::vector<int32_t> uflags;
+    for (int p = 0; p < nprob; ++p) {
+        rom_handle* h = P.handles[p];
+        ProblemDev& pd = P.probs[p];
+        pd.uflag_off = (int64_t)uflags.size();
+        const int nx = pd.nx, ny = pd.ny;
+        for (int quad = 0; quad < 4; ++quad) {
+            const bool xpos = (quad == 0 || quad == 3), ypos = (quad < 2);
+            for (int st = 0; st < pd.nstrips; ++st) {
+                for (int c = 0; c < pd.nchunks; ++c) {
+                    int32_t mask = 0;
+                    for (int r = 0; r < TY; ++r) {
+                        const int jj = st * TY + r;
+                        if (jj >= ny) break;
+                        const int j = ypos ? jj : ny - 1 - jj;
+                        bool uni = true;
+                        double v0 = 0.0;
+                        for (int i = 0; i < TX; ++i) {
+                            const int ii = c * TX + i;
+                            if (ii >= nx) break;
+                            const double v = h->st[(size_t)j * nx + (xpos ? ii : nx - 1 - ii)];
+                            if (i == 0) v0 = v;
+                            else if (v != v0) uni = false;
+                        }
+                        if (uni) mask |= 1 << r;
+                    }
+                    uflags.push_back(mask);
+                }
+            }
+        }
     }
 
     // lanes per group: smallest of 16/32/64 covering the largest per-quadrant count of a problem
@@ -481,6 +527,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     upload(P.d_slot_off, P.slot_off);
     upload(P.d_slot_order, P.slot_order);
     upload(P.d_cblocks, P.cblocks);
+    upload(P.d_uflags, uflags);
 
     auto cast_upload = [&](DevMem& d, const std::vector<double>& v) {
         if (P.fp64) {
@@ -595,7 +642,7 @@ void build_kernel_matrices(Plan& P, const std::vector<SysInput>& in)
     else upload(P.d_Pt, bt16);
 }
 
-void enqueue_iteration(Plan& P, hipStream_t s, double tol, hipEvent_t e_start = nullptr, hipEvent_t e_stop = nullptr)
+void enqueue_iteration(Plan& P, hipStream_t s, double tol)
 {
     if (P.aniso) {
         for (int k = 0; k < P.nsys; ++k) {
@@ -614,9 +661,7 @@ void enqueue_iteration(Plan& P, hipStream_t s, double tol, hipEvent_t e_start = 
         }
     }
     const SweepArgs sa = P.sweep_args(0, 0);
-    if (e_start) HIPCHK(hipEventRecord(e_start, s));
     HIPCHK(launch_sweep(sa, P.grid, P.fp64, P.tx, P.ty, P.dd, P.aniso, P.aniso ? (P.fp64 ? 1 : 2) : 0, s));
-    if (e_stop) HIPCHK(hipEventRecord(e_stop, s));
     const CombineArgs ca = P.combine_args(0, tol);
     HIPCHK(launch_combine(ca, (int)P.cblocks.size(), P.fp64, s));
 }
@@ -659,8 +704,7 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     }
     HIPCHK(launch_reset_systems(P.d_sysctl.as<SysCtl>(), P.nsys, P.d_ctl.as<Ctl>(), s));
 
-    const int timing = o.timing ? 1 : 0;
-    if (!P.gexec || P.graph_iters != K || P.graph_stream != s || P.graph_timing != timing || P.graph_tol != tol) {
+    if (!P.gexec || P.graph_iters != K || P.graph_stream != s || P.graph_tol != tol) {
         if (P.gexec) {
             (void)hipGraphExecDestroy(P.gexec);
             P.gexec = nullptr;
@@ -669,16 +713,9 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
             (void)hipGraphDestroy(P.graph);
             P.graph = nullptr;
         }
-        for (auto e : P.ev) (void)hipEventDestroy(e);
-        P.ev.clear();
-        if (timing) {
-            P.ev.resize(2 * K);
-            for (auto& e : P.ev) HIPCHK(hipEventCreate(&e));
-        }
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
-            for (int k = 0; k < K; ++k)
-                enqueue_iteration(P, s, tol, timing ? P.ev[2 * k] : nullptr, timing ? P.ev[2 * k + 1] : nullptr);
+            for (int k = 0; k < K; ++k) enqueue_iteration(P, s, tol);
         } catch (...) {
             hipGraph_t g;
             (void)hipStreamEndCapture(s, &g);
@@ -689,29 +726,15 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
         HIPCHK(hipGraphInstantiate(&P.gexec, P.graph, nullptr, nullptr, 0));
         P.graph_iters = K;
         P.graph_stream = s;
-        P.graph_timing = timing;
         P.graph_tol = tol;
     }
     Ctl ctl{};
     int launched = 0;
-    double sweep_ms = 0.0;
-    int sweeps = 0;
-    int active_before = P.nsys;
     for (;;) {
         HIPCHK(hipGraphLaunch(P.gexec, s));
         launched += K;
         HIPCHK(hipMemcpyAsync(&ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
-        if (timing && active_before > 0) {
-            // sweeps of an already finished solve return at once; count the ones that ran
-            for (int k = 0; k < K; ++k) {
-                float t = 0.f;
-                HIPCHK(hipEventElapsedTime(&t, P.ev[2 * k], P.ev[2 * k + 1]));
-                sweep_ms += t;
-                ++sweeps;
-            }
-        }
-        active_before = ctl.active;
         if (ctl.error || ctl.active == 0 || launched >= P.max_iter + K) break;
     }
     HIPCHK(hipEventRecord(e1, s));
@@ -723,8 +746,8 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     r.error = ctl.error != 0;
-    r.sweep_ms = sweep_ms;
-    r.sweeps = sweeps;
+    r.sweep_ms = (double)ctl.sweep_ticks / wallclock_khz();
+    r.sweeps = ctl.sweeps;
     r.sc.resize(P.nsys);
     HIPCHK(hipMemcpy(r.sc.data(), P.d_sysctl.p, P.nsys * sizeof(SysCtl), hipMemcpyDeviceToHost));
     return r;

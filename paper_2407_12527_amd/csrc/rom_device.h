@@ -29,6 +29,7 @@ struct ProblemDev {
     int32_t nchunks;      // ceil(nx / TX)
     int32_t nstrips;      // ceil(ny / TY)
     int64_t field_off;    // offset of sigma_t / sigma_s / q in the field pools (elements)
+    int64_t uflag_off;    // offset of the row-uniformity masks [4 quadrants][nstrips][nchunks]
 };
 
 struct WaveStreamDev {
@@ -77,8 +78,10 @@ struct Ctl {
     int32_t blocks_done;    // combine blocks finished in this iteration
     int32_t active;         // systems still running after the last combine step
     int32_t error;          // 1: a dependency wait timed out
-    int32_t launches;       // sweeps launched
-    int32_t pad[2];
+    int32_t sweeps;         // sweep launches that did work (timed)
+    unsigned long long t_first;     // real-time clock at the first wave start of the running sweep
+    unsigned long long t_last;      // ... and at the last wave end
+    unsigned long long sweep_ticks; // summed sweep durations (real-time clock ticks)
 };
 
 }  // namespace rom

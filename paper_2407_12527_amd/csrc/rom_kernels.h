@@ -23,6 +23,8 @@ struct SweepArgs {
     void* psi_out;             // angular-flux output pool [cells][npad] (T or BF16)
     void* part;                // partial scalar-flux pool (T)
     const int64_t* slot_off;   // partial slot -> offset in part
+    const int32_t* uflags;     // per (problem, quadrant, strip, chunk): bit r set when sigma_t is
+                               // constant along row r of the chunk
     void* edge;                // strip-edge pool (T)
     const void* inflow;        // boundary inflow pool (T)
     long long* prog;           // strip progress counters
