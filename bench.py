@@ -46,7 +46,21 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(DESCR))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run a device-to-device copy of BYTES (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def calibrate_copy(nbytes):
+    """A plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters give the scale
+    factor between the counters and bytes moved."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibrate_copy_bytes": nbytes, "copies": 3}), flush=True)
 
 
 def cpu_baseline(workload, seconds):
@@ -82,6 +96,9 @@ def cpu_baseline(workload, seconds):
 
 def main():
     a = parse()
+    if a.calibrate_copy:
+        calibrate_copy(a.calibrate_copy)
+        return
     if a.gpus != 1:
         print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported", file=sys.stderr)
         sys.exit(2)

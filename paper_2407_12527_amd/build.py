@@ -38,29 +38,32 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every source under csrc/ and link `out` (default: the in-tree librom.so).
+    `defines` are extra -D flags for the device sources (build variants for A/B timing)."""
+    build_dir = BUILD if not defines else BUILD + "_" + "_".join(d.replace("=", "") for d in defines)
+    os.makedirs(build_dir, exist_ok=True)
     hipcc = _hipcc()
     jobs = []
     objs = []
     for src in sorted(os.listdir(CSRC)):
         path = os.path.join(CSRC, src)
-        obj = os.path.join(BUILD, src + ".o")
+        obj = os.path.join(build_dir, src + ".o")
         if src.endswith(".hip"):
-            jobs.append([hipcc, *DEVICE_FLAGS, "-c", path, "-o", obj])
+            jobs.append([hipcc, *DEVICE_FLAGS, *[f"-D{d}" for d in defines], "-c", path, "-o", obj])
         elif src.endswith(".cpp"):
             jobs.append([hipcc, *HOST_FLAGS, "-c", path, "-o", obj])
         else:
             continue
         objs.append(obj)
     with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
-        for out in ex.map(_run, jobs):
-            if verbose and out.strip():
-                print(out)
-    tmp = LIB + ".tmp"
+        for log in ex.map(_run, jobs):
+            if verbose and log.strip():
+                print(log)
+    tmp = out + ".tmp"
     _run([hipcc, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs])
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
 
 
 if __name__ == "__main__":

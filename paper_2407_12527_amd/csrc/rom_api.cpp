@@ -297,6 +297,9 @@ void choose_tiles(const rom_si_opts& o, const std::vector<SysInput>& in, bool fp
     if (in.size() == 1 && maxside <= 512) {
         tx = 8;
         ty = 4;
+    } else if (in.size() == 1) {
+        tx = 8;
+        ty = 8;
     } else {
         tx = 16;
         ty = 16;
@@ -514,7 +517,13 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
             if (st < P.probs[P.ws[k].prob].nstrips) P.tickets.push_back(make_int2(k, st));
     P.ntickets = (int)P.tickets.size();
     P.grid = std::max(1, std::min(P.ntickets, device_cus() * 8));
-    // combine blocks
+    // combine blocks: about 512 blocks per launch (each thread keeps 4 cells in flight)
+    {
+        int64_t tot = 0;
+        for (auto& si : in) tot += si.h->cells;
+        int64_t cpb = (tot / 512 + 1023) / 1024 * 1024;
+        P.cells_per_block = (int)std::max<int64_t>(1024, std::min<int64_t>(cpb, 16384));
+    }
     for (int s = 0; s < P.nsys; ++s)
         for (int64_t c0 = 0; c0 < in[s].h->cells; c0 += P.cells_per_block) P.cblocks.push_back(make_int2(s, (int)c0));
 

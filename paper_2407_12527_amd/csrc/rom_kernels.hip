@@ -59,6 +59,11 @@ __device__ __forceinline__ void wait_progress(long long* p, long long target, Ct
 template <typename T>
 __device__ __forceinline__ T to_T(double x) { return (T)x; }
 
+#ifndef ROM_ROW_UNROLL
+#define ROM_ROW_UNROLL 0
+#endif
+
+
 // ------------------------------------------------------------------------------------ sweep
 //
 // One wavefront = one wave-stream strip task at a time.  Lane state while walking a strip:
@@ -308,7 +313,19 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs A)
         };
         T pst[PER];
         T pS[NG > 0 ? NG : 1][PER];
+        // anisotropic sources are per (cell, ordinate): each lane prefetches its own ordinate's
+        // values for the whole next chunk (one coalesced 256-byte load per cell)
+        constexpr int CA = ANG ? CH : 1;
+        T pA[CA], cA[CA];
         auto prefetch = [&](int c) {
+            if constexpr (ANG) {
+#pragma unroll
+                for (int e = 0; e < CH; ++e) {
+                    bool inside;
+                    const int cell = elem_cell(c, e, inside);
+                    pA[e] = Ap[(int64_t)cell * npad];
+                }
+            }
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int e = lane + k * kWave;
@@ -325,6 +342,10 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs A)
             }
         };
         auto commit = [&]() {
+            if constexpr (ANG) {
+#pragma unroll
+                for (int e = 0; e < CH; ++e) cA[e] = pA[e];
+            }
 #pragma unroll
             for (int k = 0; k < PER; ++k) {
                 const int e = lane + k * kWave;
@@ -357,17 +378,14 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs A)
                 for (int i = 0; i < TX; ++i)
                     yd[i] = (i < cols) ? edge_load(edge_below + (int64_t)(i0 + i) * kWave + lane) : T(0);
             }
-            for (int r = 0; r < rows; ++r) {
+            auto do_row = [&](const int r) {
                 const int jj = j0 + r;
                 const int j = ypos ? jj : ny - 1 - jj;
                 const int64_t rowbase = (int64_t)j * nx;
                 T Sv[TX], acc[TX];
                 if constexpr (ANG) {
 #pragma unroll
-                    for (int i = 0; i < TX; ++i) {
-                        const int ii = min(i0 + i, nx - 1);
-                        Sv[i] = Ap[(rowbase + (xpos ? ii : nx - 1 - ii)) * npad];
-                    }
+                    for (int i = 0; i < TX; ++i) Sv[i] = cA[r * TX + i];
                 } else {
 #pragma unroll
                     for (int i = 0; i < TX; ++i) Sv[i] = lds_S[g][r * TX + i];
@@ -422,6 +440,13 @@ __global__ __launch_bounds__(64) void sweep_kernel(SweepArgs A)
                 }
                 const RowCtx R{lane, g, L, rowbase, i0, nx, xpos, cols};
                 store_partials<TX>(R, acc, my_part);
+            };
+            if constexpr (ANG || ROM_ROW_UNROLL) {
+#pragma unroll
+                for (int r = 0; r < TY; ++r)
+                    if (r < rows) do_row(r);
+            } else {
+                for (int r = 0; r < rows; ++r) do_row(r);
             }
             if (publish) {
 #pragma unroll
@@ -447,7 +472,8 @@ __device__ void finalize_iteration(const CombineArgs& A)
     for (int s = 0; s < A.nsys; ++s) {
         SysCtl& c = A.sysctl[s];
         if (c.state != 0) continue;
-        const double d = bitsd(c.dmax_bits), p = bitsd(c.pmax_bits);
+        const double d = bitsd(__hip_atomic_load(&c.dmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+        const double p = bitsd(__hip_atomic_load(&c.pmax_bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
         const double r = p > 0.0 ? d / p : 0.0;
         c.r_prev = c.r;
         c.r = r;
@@ -486,37 +512,63 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs A)
         T* __restrict__ src = (T*)A.src + SD.src_off;
         const T* __restrict__ ss = (const T*)A.sigma_s + P.field_off;
         const T* __restrict__ q = (const T*)A.q + P.field_off;
+        const int ns = SD.nslots;
+        const int64_t* __restrict__ soff = A.slot_off;
+        const int32_t* __restrict__ sord = A.slot_order + SD.slot_first;
         const int c1 = min(cells, blk.y + A.cells_per_block);
-        for (int cell = blk.y + tid; cell < c1; cell += blockDim.x) {
-            T v = T(0);
-            for (int k = 0; k < SD.nslots; ++k) v += part[A.slot_off[A.slot_order[SD.slot_first + k]] + cell];
-            const double d = fabs((double)v - (double)phi[cell]);
-            dmax = fmax(dmax, d);
-            pmax = fmax(pmax, fabs((double)v));
-            phi[cell] = v;
-            src[cell] = fma(ss[cell], v, q[cell]);
+        constexpr int U = 4;  // cells per thread in flight
+        for (int base = blk.y + tid; base < c1; base += 256 * U) {
+            T v[U];
+            T old[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int cell = base + u * 256;
+                v[u] = T(0);
+                old[u] = cell < c1 ? phi[cell] : T(0);
+            }
+            for (int k = 0; k < ns; ++k) {
+                const T* __restrict__ pk = part + soff[sord[k]];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int cell = base + u * 256;
+                    if (cell < c1) v[u] += pk[cell];
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int cell = base + u * 256;
+                if (cell < c1) {
+                    dmax = fmax(dmax, fabs((double)v[u] - (double)old[u]));
+                    pmax = fmax(pmax, fabs((double)v[u]));
+                    phi[cell] = v[u];
+                    src[cell] = fma(ss[cell], v[u], q[cell]);
+                }
+            }
         }
     }
-    __shared__ double sd[256], sp[256];
-    sd[tid] = dmax;
-    sp[tid] = pmax;
+    // block maxima: wave reduction, then across the 4 waves
+    for (int off = 32; off > 0; off >>= 1) {
+        dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+        pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
+    }
+    __shared__ double sd[4], sp[4];
+    if ((tid & 63) == 0) {
+        sd[tid >> 6] = dmax;
+        sp[tid >> 6] = pmax;
+    }
     __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) {
-            sd[tid] = fmax(sd[tid], sd[tid + o]);
-            sp[tid] = fmax(sp[tid], sp[tid + o]);
-        }
-        __syncthreads();
-    }
     if (tid == 0) {
+        dmax = fmax(fmax(sd[0], sd[1]), fmax(sd[2], sd[3]));
+        pmax = fmax(fmax(sp[0], sp[1]), fmax(sp[2], sp[3]));
         if (run && A.mode == 0) {
-            atomicMax(&A.sysctl[s].dmax_bits, dbits(sd[0]));  // non-negative doubles order as integers
-            atomicMax(&A.sysctl[s].pmax_bits, dbits(sp[0]));
+            atomicMax(&A.sysctl[s].dmax_bits, dbits(dmax));  // non-negative doubles order as integers
+            atomicMax(&A.sysctl[s].pmax_bits, dbits(pmax));
         }
-        __threadfence();
+        // The maxima are device-scope atomics; waiting for their completion before counting the
+        // block in is all the last block needs (the fluxes themselves are read by later kernels).
+        stores_complete();
         const int done = atomicAdd(&A.ctl->blocks_done, 1);
         if (done == (int)gridDim.x - 1) {
-            __threadfence();
             if (A.mode == 0) finalize_iteration(A);
             if (A.ctl->t_last > A.ctl->t_first && A.ctl->t_first != ~0ull) {
                 A.ctl->sweep_ticks += A.ctl->t_last - A.ctl->t_first;
@@ -527,7 +579,6 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs A)
             A.ctl->blocks_done = 0;
             A.ctl->ticket = 0;
             A.ctl->epoch += 1;
-            __threadfence();
         }
     }
 }
@@ -631,8 +682,13 @@ __global__ __launch_bounds__(256) void contract_bf16_kernel(ContractArgs A)
     const int wm = wave / 2, wn = wave % 2;
     // XCD-aware block order is left to the dispatcher; blocks walk N fastest so that one A tile
     // (the large operand) is reused from L2 by the N/GN blocks that follow it.
+    // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Renumber them
+    // so that every XCD owns a contiguous run of logical tiles: the N/GN tiles that share one A
+    // row-block then run on the same XCD and read A from HBM once.
     const int nblk_n = A.N / GN;
-    const int bm = blockIdx.x / nblk_n, bn = blockIdx.x % nblk_n;
+    const int nb = gridDim.x;
+    const int lb = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+    const int bm = lb / nblk_n, bn = lb % nblk_n;
     const int m0 = bm * GM, n0 = bn * GN;
     const __bf16* __restrict__ Ag = (const __bf16*)A.a;
     const __bf16* __restrict__ Bg = (const __bf16*)A.bt;

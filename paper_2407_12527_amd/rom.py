@@ -72,6 +72,10 @@ class rom_ens_stats(C.Structure):
 
 
 def library_path() -> str:
+    """The in-tree librom.so, or the file named by the ROM_LIBRARY environment variable."""
+    env = os.environ.get("ROM_LIBRARY")
+    if env:
+        return env
     return os.path.join(os.path.dirname(os.path.abspath(__file__)), "librom.so")
 
 
