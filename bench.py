@@ -46,6 +46,8 @@ def parse():
     ap.add_argument("--workload", default="c2", choices=sorted(DESCR))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--tile", default="0x0", help="sweep chunk x strip size, e.g. 8x4 (0x0: automatic)")
+    ap.add_argument("--band", type=int, default=0, help="strips per sweep workgroup (0: automatic)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (reference for HBM byte counters)")
     return ap.parse_args()
@@ -112,7 +114,8 @@ def main():
     n = wl.n_ord[0]
     fp64 = wl.precision == "fp64"
     prec = R.ROM_PREC_FP64 if fp64 else R.ROM_PREC_FP32
-    opts = R.si_opts(tol=wl.tol, max_iter=wl.max_iter, precision=prec)
+    tile = tuple(int(v) for v in a.tile.lower().split("x"))
+    opts = R.si_opts(tol=wl.tol, max_iter=wl.max_iter, precision=prec, tile=tile, band=a.band)
     if wl.ord_kind == "stratified":
         m = n // 4
         nz = max(d for d in range(1, int(m ** 0.5) + 1) if m % d == 0)

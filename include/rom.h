@@ -103,7 +103,8 @@ typedef struct {
     int32_t iters_per_check;  /* iterations captured per graph replay between host checks; 0 -> auto */
     int32_t tile_x, tile_y;   /* sweep chunk / strip size in cells; 0 -> autotuned */
     int32_t contract_split;   /* reserved for a split-BF16 contraction; must be 0 */
-    int32_t reserved[4];
+    int32_t band;             /* consecutive strips per sweep workgroup (1..8); 0 -> automatic */
+    int32_t reserved[3];
 } rom_si_opts;
 
 typedef struct {

@@ -154,6 +154,8 @@ struct SysInput {
 struct Plan {
     bool fp64 = false, dd = false, aniso = false;
     int tx = 16, ty = 16;
+    int band = 1;   // strips per sweep workgroup
+    int L = 64;     // lanes per ordinate group
     int esz = 4;
     int nsys = 0, nws = 0, ntickets = 0, nslots = 0;
     int grid = 1;
@@ -200,6 +202,7 @@ struct Plan {
         a.ntickets = ntickets;
         a.spin_limit = 1 << 24;
         a.mode_all = mode_all;
+        a.band = band;
         a.sigma_t = d_st.p;
         a.src = d_src.p;
         a.ang_src = d_ang.p;
@@ -307,7 +310,8 @@ void choose_tiles(const rom_si_opts& o, const std::vector<SysInput>& in, bool fp
 }
 
 // Build every table and buffer of a plan for the given systems.
-void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, bool aniso, int max_iter)
+void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, bool aniso, int max_iter,
+                bool psi_out = false)
 {
     P.fp64 = o.precision == ROM_PREC_FP64;
     P.dd = o.scheme == ROM_SCHEME_DD;
@@ -315,7 +319,8 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     P.esz = P.fp64 ? 8 : 4;
     P.max_iter = max_iter;
     choose_tiles(o, in, P.fp64, P.tx, P.ty);
-    if (!sweep_tile_supported(P.tx, P.ty)) throw Fail{ROM_E_ARG, "unsupported tile shape"};
+    if (!(P.fp64 ? sweep_tile_supported_fp64(P.tx, P.ty) : sweep_tile_supported(P.tx, P.ty)))
+        throw Fail{ROM_E_ARG, P.fp64 ? "FP64 sweeps support tiles 8x4 and 8x8" : "unsupported tile shape"};
     const int TX = P.tx, TY = P.ty;
 
     // problems = distinct handles, in first-appearance order
@@ -375,20 +380,33 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         }
     }
 
-    // lanes per group: smallest of 16/32/64 covering the largest per-quadrant count of a problem
-    std::vector<int> Lp(nprob, 16);
+    // lanes per group: the smallest of 16/32/64 covering the largest per-quadrant ordinate count
+    // of the batch (64 for anisotropic sources and angular-flux output, which use 64-lane groups)
     struct QuadList {
         std::vector<int> idx[4];
     };
     std::vector<QuadList> ql(in.size());
+    int Lb = (aniso || psi_out) ? 64 : 16;
     for (size_t k = 0; k < in.size(); ++k) {
         for (int l = 0; l < in[k].n; ++l) ql[k].idx[quadrant_of(in[k].dirs[3 * l], in[k].dirs[3 * l + 1])].push_back(l);
-        const int p = pidx[in[k].h];
         for (int q = 0; q < 4; ++q) {
             const int m = (int)ql[k].idx[q].size();
-            while (Lp[p] < 64 && Lp[p] < m) Lp[p] *= 2;
+            while (Lb < 64 && Lb < m) Lb *= 2;
         }
     }
+    P.L = Lb;
+    std::vector<int> Lp(nprob, Lb);
+    {
+        // strips per workgroup: a band long enough that most hand-offs stay in LDS
+        int maxstrips = 1;
+        for (auto& si : in) maxstrips = std::max(maxstrips, (si.h->grid.ny + TY - 1) / TY);
+        P.band = o.band > 0 ? o.band : std::min(kMaxBand, maxstrips);
+        // keep the workgroup's LDS within 64 KiB when choosing automatically (two workgroups per CU)
+        while (o.band == 0 && P.band > 1 && sweep_lds_bytes(P.fp64, TX, TY, aniso, P.L, P.band) > 64 * 1024) --P.band;
+        if (sweep_lds_bytes(P.fp64, TX, TY, aniso, P.L, P.band) > 160 * 1024)
+            throw Fail{ROM_E_ARG, "band too large for this tile shape (LDS)"};
+    }
+
 
     // systems: internal (quadrant-grouped, padded) ordinate order
     P.nsys = (int)in.size();
@@ -452,10 +470,11 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
                 W.prob = p;
                 W.quad = q;
                 W.L = L;
+                const int nbands = (pd.nstrips + P.band - 1) / P.band;
                 W.prog_off = prog_sum;
-                prog_sum += pd.nstrips;
+                prog_sum += nbands;
                 W.edge_off = edge_sum;
-                edge_sum += (int64_t)pd.nstrips * pd.nx * kWave;
+                edge_sum += (int64_t)nbands * pd.nx * kWave;
                 W.xin_off = W.yin_off = -1;
                 if (!vacuum) {
                     W.xin_off = inflow_sum;
@@ -509,14 +528,14 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         std::sort(key.begin(), key.end());
         for (auto& kv : key) P.slot_order.push_back(kv.second);
     }
-    // tickets: strip-major, so every strip's producer precedes it
-    int maxstrips = 0;
-    for (auto& pd : P.probs) maxstrips = std::max(maxstrips, pd.nstrips);
-    for (int st = 0; st < maxstrips; ++st)
+    // tickets: (wave-stream, band), band-major, so every band's producer precedes it
+    int maxbands = 0;
+    for (auto& pd : P.probs) maxbands = std::max(maxbands, (pd.nstrips + P.band - 1) / P.band);
+    for (int bd = 0; bd < maxbands; ++bd)
         for (int k = 0; k < P.nws; ++k)
-            if (st < P.probs[P.ws[k].prob].nstrips) P.tickets.push_back(make_int2(k, st));
+            if (bd < (P.probs[P.ws[k].prob].nstrips + P.band - 1) / P.band) P.tickets.push_back(make_int2(k, bd));
     P.ntickets = (int)P.tickets.size();
-    P.grid = std::max(1, std::min(P.ntickets, device_cus() * 8));
+    P.grid = std::max(1, std::min(P.ntickets, device_cus() * 4));
     // combine blocks: about 512 blocks per launch (each thread keeps 4 cells in flight)
     {
         int64_t tot = 0;
@@ -670,7 +689,7 @@ void enqueue_iteration(Plan& P, hipStream_t s, double tol)
         }
     }
     const SweepArgs sa = P.sweep_args(0, 0);
-    HIPCHK(launch_sweep(sa, P.grid, P.fp64, P.tx, P.ty, P.dd, P.aniso, P.aniso ? (P.fp64 ? 1 : 2) : 0, s));
+    HIPCHK(launch_sweep(sa, P.grid, P.fp64, P.tx, P.ty, P.dd, P.aniso, P.aniso ? (P.fp64 ? 1 : 2) : 0, P.L, s));
     const CombineArgs ca = P.combine_args(0, tol);
     HIPCHK(launch_combine(ca, (int)P.cblocks.size(), P.fp64, s));
 }
@@ -787,6 +806,7 @@ int validate_opts(rom_handle* h, const rom_si_opts* o, rom_si_opts& out)
     if (out.scheme != ROM_SCHEME_STEP && out.scheme != ROM_SCHEME_DD) return fail(h, ROM_E_ARG, "bad scheme");
     if (out.iters_per_check < 0) return fail(h, ROM_E_ARG, "iters_per_check must be >= 0");
     if (out.contract_split != 0) return fail(h, ROM_E_UNSUPPORTED, "split contraction is not built");
+    if (out.band < 0 || out.band > kMaxBand) return fail(h, ROM_E_ARG, "band must be 0..8");
     if ((out.tile_x != 0 || out.tile_y != 0) && !sweep_tile_supported(out.tile_x, out.tile_y))
         return fail(h, ROM_E_ARG, "unsupported tile shape (8x4, 8x8, 16x8, 16x16, 32x16)");
     return ROM_OK;
@@ -795,8 +815,8 @@ int validate_opts(rom_handle* h, const rom_si_opts* o, rom_si_opts& out)
 std::string plan_signature(const rom_si_opts& o, bool aniso, int kind, int nsys)
 {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "k%d p%d s%d t%dx%d a%d n%d mi%d", kind, o.precision, o.scheme, o.tile_x, o.tile_y,
-                  (int)aniso, nsys, o.max_iter);
+    std::snprintf(buf, sizeof buf, "k%d p%d s%d t%dx%d b%d a%d n%d mi%d", kind, o.precision, o.scheme, o.tile_x, o.tile_y,
+                  o.band, (int)aniso, nsys, o.max_iter);
     return buf;
 }
 
@@ -993,7 +1013,7 @@ int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double
             if (!isfin(src[k])) return fail(h, ROM_E_DOMAIN, "non-finite source");
         std::vector<SysInput> in{{h, h->dirs.data(), h->w.data(), h->n, true}};
         std::unique_ptr<Plan> P(new Plan());
-        build_plan(*P, in, o, per, 0);
+        build_plan(*P, in, o, per, 0, psi != nullptr);
         hipStream_t s = h->stream();
         const SystemDev& sd = P->sys[0];
         const int al = P->npad_al[0];
@@ -1025,7 +1045,7 @@ int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double
         HIPCHK(launch_reset_systems(P->d_sysctl.as<SysCtl>(), 1, P->d_ctl.as<Ctl>(), s));
         SweepArgs sa = P->sweep_args(1, psi_mode);
         // the sweep writes psi' into the angular layout when asked for it
-        HIPCHK(launch_sweep(sa, P->grid, P->fp64, P->tx, P->ty, P->dd, per, psi_mode, s));
+        HIPCHK(launch_sweep(sa, P->grid, P->fp64, P->tx, P->ty, P->dd, per, psi_mode, P->L, s));
         const CombineArgs ca = P->combine_args(1, 0.0);
         HIPCHK(launch_combine(ca, (int)P->cblocks.size(), P->fp64, s));
         Ctl ctl{};

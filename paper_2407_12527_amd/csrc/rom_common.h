@@ -1,0 +1,79 @@
+// rom_common.h -- device helpers shared by the gfx950 kernels of librom.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <hip/hip_bf16.h>
+#include <stdint.h>
+
+#include "rom_device.h"
+#include "rom_kernels.h"
+
+namespace rom {
+
+// ------------------------------------------------------------------------------------ helpers
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp_fast(double x) { return 1.0 / x; }
+
+__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
+__device__ __forceinline__ int64_t uniform64(int64_t x)
+{
+    const int lo = __builtin_amdgcn_readfirstlane((int)(x & 0xffffffff));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(x >> 32));
+    return ((int64_t)hi << 32) | (unsigned)lo;
+}
+
+// Strip-edge hand-off between wavefronts that may sit on different XCDs.  The edge words
+// themselves are written and read with device-scope (agent) relaxed atomic accesses, which the
+// hardware keeps coherent across the per-XCD L2 caches word by word; the producer then waits for
+// its stores to complete (s_waitcnt vmcnt(0)) before it publishes the progress counter.  This
+// avoids the whole-L2 write-back / invalidate that a release / acquire fence pair costs.
+template <typename T>
+__device__ __forceinline__ void edge_store(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+template <typename T>
+__device__ __forceinline__ T edge_load(const T* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
+
+__device__ __forceinline__ void stores_complete() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Wait until *p >= target (the strip below has finished chunk c of this epoch).  Bounded: after
+// `limit` polls (or once another wave has timed out) the wait gives up and records the error, so
+// every wave always exits.
+__device__ __forceinline__ void wait_progress(long long* p, long long target, Ctl* ctl, int limit)
+{
+    int spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins >= limit) {
+            __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        if ((spins & 1023) == 0 &&
+            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            break;
+    }
+    asm volatile("" ::: "memory");  // edge loads stay after the poll
+}
+
+// Wait until an LDS counter of the workgroup reaches `target` (bounded like wait_progress).
+__device__ __forceinline__ void lds_wait(int* p, int target, Ctl* ctl, int limit)
+{
+    int spins = 0;
+    while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins >= limit) {
+            __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+        }
+        if ((spins & 1023) == 0 &&
+            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
+            break;
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ T to_T(double x) { return (T)x; }
+
+#ifndef ROM_ROW_UNROLL
+#define ROM_ROW_UNROLL 0
+#endif
+
+
+}  // namespace rom

@@ -23,6 +23,8 @@ namespace rom {
 
 constexpr int kWave = 64;
 constexpr int kMaxGroups = 4;
+constexpr int kMaxBand = 8;    // wavefronts (consecutive strips) per sweep workgroup
+constexpr int kRingSlots = 2;  // LDS ring slots per strip boundary inside a band
 
 struct ProblemDev {
     int32_t nx, ny;
@@ -36,8 +38,8 @@ struct WaveStreamDev {
     int32_t prob;               // problem index
     int32_t quad;               // 0: c>=0,s>=0  1: c<0,s>=0  2: c<0,s<0  3: c>=0,s<0
     int32_t L;                  // lanes per group (16, 32, 64)
-    int32_t prog_off;           // first progress counter (one per strip)
-    int64_t edge_off;           // strip-edge buffer [nstrips][nx][64] (elements of T)
+    int32_t prog_off;           // first progress counter (one per band of strips)
+    int64_t edge_off;           // band-top edge buffer [nbands][nx][64] (elements of T)
     int64_t xin_off;            // inflow on the entry x-face [ny][64] in sweep order, -1 = vacuum
     int64_t yin_off;            // inflow on the entry y-face [nx][64] in sweep order, -1 = vacuum
     int32_t sys[kMaxGroups];    // system of each group (-1: empty group)

@@ -12,11 +12,11 @@ struct SweepArgs {
     const WaveStreamDev* ws;
     const LaneDev* lanes;      // [nws][64]
     const SystemDev* sys;
-    const int2* tickets;       // (wave-stream, strip), strip-major
+    const int2* tickets;       // (wave-stream, band), band-major
     int32_t ntickets;
     int32_t spin_limit;        // polls before a dependency wait gives up
     int32_t mode_all;          // 1: sweep every wave-stream regardless of convergence state
-    int32_t pad;
+    int32_t band;              // wavefronts per workgroup = consecutive strips per ticket (1..8)
     const void* sigma_t;       // field pool (T)
     const void* src;           // isotropic source pool (T)
     const void* ang_src;       // per-ordinate source pool [cells][npad] (T)
@@ -75,9 +75,12 @@ struct ContractArgs {
     const SysCtl* sysctl;      // skip when that system has stopped (NULL: always run)
 };
 
-hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty, bool dd, bool ang, int psi,
+// L = lanes per ordinate group (16, 32 or 64; 64 for anisotropic sources and psi output)
+hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty, bool dd, bool ang, int psi, int L,
                         hipStream_t s);
 bool sweep_tile_supported(int tx, int ty);
+bool sweep_tile_supported_fp64(int tx, int ty);
+size_t sweep_lds_bytes(bool fp64, int tx, int ty, bool ang, int L, int nw);
 hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s);
 hipError_t launch_sweep_prologue(Ctl* ctl, hipStream_t s);
 hipError_t launch_reset_systems(SysCtl* sc, int nsys, Ctl* ctl, hipStream_t s);

@@ -1,8 +1,6 @@
 // rom_kernels.hip -- gfx950 (MI355X) kernels of librom.
 //
-//   sweep_kernel     transport sweep psi = L^{-1} S for every ordinate (the operator inversion of
-//                    Sec. 3.2): ordinates on wavefront lanes, persistent strip tasks, strip edges
-//                    handed upward through global memory behind epoch-tagged progress counters;
+//   (sweep_kernel lives in rom_sweep.h, instantiated per tile shape in rom_sweep_*.hip)
 //   combine_kernel   phi = sum of the per-group partial fluxes in a fixed order, the next
 //                    isotropic source sigma_s phi + q, the FP64 relative change and the
 //                    per-system convergence decision of source iteration (eq. (3.10));
@@ -14,452 +12,9 @@
 #include <hip/hip_bf16.h>
 #include <stdint.h>
 
-#include "rom_device.h"
-#include "rom_kernels.h"
+#include "rom_common.h"
 
 namespace rom {
-
-// ------------------------------------------------------------------------------------ helpers
-__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
-__device__ __forceinline__ double rcp_fast(double x) { return 1.0 / x; }
-
-__device__ __forceinline__ int uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
-
-// Strip-edge hand-off between wavefronts that may sit on different XCDs.  The edge words
-// themselves are written and read with device-scope (agent) relaxed atomic accesses, which the
-// hardware keeps coherent across the per-XCD L2 caches word by word; the producer then waits for
-// its stores to complete (s_waitcnt vmcnt(0)) before it publishes the progress counter.  This
-// avoids the whole-L2 write-back / invalidate that a release / acquire fence pair costs.
-template <typename T>
-__device__ __forceinline__ void edge_store(T* p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-template <typename T>
-__device__ __forceinline__ T edge_load(const T* p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-
-__device__ __forceinline__ void stores_complete() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
-
-// Wait until *p >= target (the strip below has finished chunk c of this epoch).  Bounded: after
-// `limit` polls (or once another wave has timed out) the wait gives up and records the error, so
-// every wave always exits.
-__device__ __forceinline__ void wait_progress(long long* p, long long target, Ctl* ctl, int limit)
-{
-    int spins = 0;
-    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins >= limit) {
-            __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
-        }
-        if ((spins & 1023) == 0 &&
-            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-            break;
-    }
-    asm volatile("" ::: "memory");  // edge loads stay after the poll
-}
-
-template <typename T>
-__device__ __forceinline__ T to_T(double x) { return (T)x; }
-
-#ifndef ROM_ROW_UNROLL
-#define ROM_ROW_UNROLL 0
-#endif
-
-
-// ------------------------------------------------------------------------------------ sweep
-//
-// One wavefront = one wave-stream strip task at a time.  Lane state while walking a strip:
-//   xl[r]  x-face value entering row r of the strip (carried from chunk to chunk),
-//   yd[i]  y-face value entering column i of the chunk (from the strip below, updated row by row
-//          and handed to the strip above after the chunk's last row).
-// Cell update (ordinate-scaled fluxes psi' = w psi, cells visited in sweep order):
-//   STEP: psi' = (w S + a x + b y) / (sigma_t + a + b),                x <- psi', y <- psi'
-//   DD:   psi' = (w S + 2a x + 2b y) / (sigma_t + 2a + 2b),  x <- 2psi' - x, y <- 2psi' - y
-// When sigma_t is constant along a row of a chunk (a flag the host precomputes), the reciprocal
-// of the denominator is taken once per row.
-//
-// Memory: the chunk's sigma_t and (isotropic) sources are loaded into registers one chunk ahead
-// and staged in LDS in sweep order, so the row loop reads LDS broadcasts only.  A ragged chunk or
-// strip is padded with a valid cell and a zero source; padded results are never stored.
-//
-// Scalar flux: the TX values of a row are summed over each group's lanes by a transposing
-// butterfly (gfx950 permlane swaps for lane distances 32 and 16, DPP for 8, 4, 2, 1): every
-// stage halves the number of registers, so a row of TX cells costs about 2 VALU operations per
-// cell, and the row's sums end up one cell per lane for a single coalesced store.
-
-// Lanes with bit `d` take y, the others x.
-__device__ __forceinline__ float pick(int lane, int d, float x, float y) { return (lane & d) ? y : x; }
-
-template <int D>
-__device__ __forceinline__ float halve(int lane, float x, float y)
-{
-    if constexpr (D == 32) {
-        auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
-        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    } else if constexpr (D == 16) {
-        auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
-        return __uint_as_float(r[0]) + __uint_as_float(r[1]);
-    } else {
-        // partner lane differs in bit D: row_ror:8 (xor 8), row_half_mirror (7 - l within 8 lanes),
-        // quad_perm xor 2, quad_perm xor 1
-        constexpr int CTRL = D == 8 ? 0x128 : D == 4 ? 0x141 : D == 2 ? 0x4E : 0xB1;
-        const float u = pick(lane, D, x, y);
-        const float t = pick(lane, D, y, x);
-        return u + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(t), CTRL, 0xF, 0xF, true));
-    }
-}
-
-template <int D>
-__device__ __forceinline__ float fold(float v)
-{
-    constexpr int CTRL = D == 8 ? 0x128 : D == 4 ? 0x141 : D == 2 ? 0x4E : 0xB1;
-    return v + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), CTRL, 0xF, 0xF, true));
-}
-
-// Reduce-scatter N row values over groups of L lanes; returns this lane's sum and its cell index.
-template <int N, int L>
-__device__ __forceinline__ float butterfly(int lane, float (&v)[N], int& cell)
-{
-    constexpr int LOGL = L == 64 ? 6 : L == 32 ? 5 : 4;
-    constexpr int H = N == 16 ? 4 : N == 8 ? 3 : N == 4 ? 2 : 1;
-    static_assert(H <= LOGL, "row longer than the lane group");
-    float r[N];
-#pragma unroll
-    for (int k = 0; k < N; ++k) r[k] = v[k];
-    int c = 0;
-#pragma unroll
-    for (int s = 0; s < H; ++s) {
-        const int half = N >> (s + 1);
-#pragma unroll
-        for (int k = 0; k < N / 2; ++k) {
-            if (k < half) {
-                const int d = (L == 64 ? 32 : L == 32 ? 16 : 8) >> s;
-                if (d == 32) r[k] = halve<32>(lane, r[k], r[k + half]);
-                else if (d == 16) r[k] = halve<16>(lane, r[k], r[k + half]);
-                else if (d == 8) r[k] = halve<8>(lane, r[k], r[k + half]);
-                else if (d == 4) r[k] = halve<4>(lane, r[k], r[k + half]);
-                else if (d == 2) r[k] = halve<2>(lane, r[k], r[k + half]);
-                else r[k] = halve<1>(lane, r[k], r[k + half]);
-            }
-        }
-        const int d = (L == 64 ? 32 : L == 32 ? 16 : 8) >> s;
-        c |= ((lane & d) ? 1 : 0) << (H - 1 - s);
-    }
-    float out = r[0];
-#pragma unroll
-    for (int s = H; s < LOGL; ++s) {
-        const int d = (L == 64 ? 32 : L == 32 ? 16 : 8) >> s;
-        if (d == 8) out = fold<8>(out);
-        else if (d == 4) out = fold<4>(out);
-        else if (d == 2) out = fold<2>(out);
-        else if (d == 1) out = fold<1>(out);
-    }
-    cell = c;
-    return out;
-}
-
-// Lanes whose in-place (folded) bits are zero represent their cell.
-template <int N, int L>
-__device__ __forceinline__ bool butterfly_rep(int lane)
-{
-    constexpr int LOGL = L == 64 ? 6 : L == 32 ? 5 : 4;
-    constexpr int H = N == 16 ? 4 : N == 8 ? 3 : N == 4 ? 2 : 1;
-    constexpr int FOLD_MASK = (1 << (LOGL - H)) - 1;  // folded distances are the lowest lane bits
-    return (lane & FOLD_MASK) == 0;
-}
-
-struct RowCtx {
-    int lane, g, L;
-    int64_t rowbase;
-    int i0, nx;
-    bool xpos;
-    int cols;
-};
-
-// Row scalar-flux partials: float rows use the butterfly, double rows a plain xor shuffle.
-template <int TX>
-__device__ __forceinline__ void store_partials(const RowCtx& R, float (&acc)[TX], float* p)
-{
-    int c = 0;
-    float v = 0.f;
-    bool rep = false;
-    if (R.L == 64) {
-        v = butterfly<TX, 64>(R.lane, acc, c);
-        rep = butterfly_rep<TX, 64>(R.lane);
-    } else if (R.L == 32) {
-        v = butterfly<TX, 32>(R.lane, acc, c);
-        rep = butterfly_rep<TX, 32>(R.lane);
-    } else {
-        v = butterfly<TX, 16>(R.lane, acc, c);
-        rep = butterfly_rep<TX, 16>(R.lane);
-    }
-    if (rep && p && c < R.cols) {
-        const int ii = R.i0 + c;
-        p[R.rowbase + (R.xpos ? ii : R.nx - 1 - ii)] = v;
-    }
-}
-
-template <int TX>
-__device__ __forceinline__ void store_partials(const RowCtx& R, double (&acc)[TX], double* p)
-{
-    for (int off = 1; off < R.L; off <<= 1) {
-#pragma unroll
-        for (int i = 0; i < TX; ++i) acc[i] += __shfl_xor(acc[i], off, 64);
-    }
-    if (p && (R.lane & (R.L - 1)) == 0) {
-#pragma unroll
-        for (int i = 0; i < TX; ++i) {
-            if (i < R.cols) {
-                const int ii = R.i0 + i;
-                p[R.rowbase + (R.xpos ? ii : R.nx - 1 - ii)] = acc[i];
-            }
-        }
-    }
-}
-
-template <typename T, int TX, int TY, bool DD, bool ANG, int PSI>
-__global__ __launch_bounds__(64) void sweep_kernel(SweepArgs A)
-{
-    constexpr int CH = TX * TY;
-    constexpr int PER = (CH + kWave - 1) / kWave;
-    constexpr int NG = ANG ? 0 : kMaxGroups;  // staged isotropic sources, one block per group
-    __shared__ T lds_st[CH];
-    __shared__ T lds_S[NG > 0 ? NG : 1][CH + 4];
-
-    const int lane = threadIdx.x;
-    if (!A.mode_all && A.ctl->active == 0) return;  // every system has stopped
-    // sweep duration: first wave start .. last wave end on the device real-time clock
-    if (lane == 0) atomicMin(&A.ctl->t_first, (unsigned long long)wall_clock64());
-    const int epoch = A.ctl->epoch;
-    const long long tag = (long long)epoch << 24;
-    const T* __restrict__ sigma_t = (const T*)A.sigma_t;
-    const T* __restrict__ srcp = (const T*)A.src;
-    const T* __restrict__ angp = (const T*)A.ang_src;
-    const T* __restrict__ inflow = (const T*)A.inflow;
-    T* __restrict__ part = (T*)A.part;
-    T* __restrict__ edge = (T*)A.edge;
-
-    for (;;) {
-        int t = 0;
-        if (lane == 0) t = atomicAdd(&A.ctl->ticket, 1);
-        t = uniform(__shfl(t, 0, 64));
-        if (t >= A.ntickets) break;
-        const int2 tk = A.tickets[t];
-        const int wsi = uniform(tk.x);
-        const int strip = uniform(tk.y);
-        const WaveStreamDev& W = A.ws[wsi];
-        const ProblemDev& P = A.probs[uniform(W.prob)];
-        const int L = uniform(W.L);
-        const int G = kWave / L;
-
-        // skip wave-streams whose systems have all stopped (flags change only between sweeps)
-        bool any = false;
-        for (int g = 0; g < G; ++g) {
-            const int s = W.sys[g];
-            if (s >= 0 && A.sysctl[s].state == 0) any = true;
-        }
-        if (A.mode_all) any = true;
-        if (!any) continue;
-
-        const int g = lane / L;
-        int gsys = W.sys[g];
-        if (gsys < 0) gsys = W.sys[0];
-        const int gslot = W.slot[g];
-        const LaneDev ld = A.lanes[wsi * kWave + lane];
-        const T a = to_T<T>(DD ? 2.0 * ld.a : ld.a);
-        const T b = to_T<T>(DD ? 2.0 * ld.b : ld.b);
-        const T w = to_T<T>(ld.w);
-        const T kappa = a + b;
-        const SystemDev& SD = A.sys[gsys];
-        const T* __restrict__ Ap = angp + SD.ang_off + ld.ord;
-        const int64_t npad = SD.npad;
-        // this lane's partial-flux slot, and the isotropic source of every group (uniform)
-        T* const my_part = gslot >= 0 ? part + A.slot_off[gslot] : nullptr;
-        const T* sbase[kMaxGroups];
-#pragma unroll
-        for (int k = 0; k < kMaxGroups; ++k) {
-            const int sy = (k < G && W.sys[k] >= 0) ? W.sys[k] : W.sys[0];
-            sbase[k] = srcp + A.sys[sy].src_off;
-        }
-
-        const int nx = P.nx, ny = P.ny;
-        const int quad = W.quad;
-        const bool xpos = (quad == 0 || quad == 3);
-        const bool ypos = (quad < 2);
-        const T* __restrict__ st = sigma_t + P.field_off;
-        const int32_t* __restrict__ uflags = A.uflags + P.uflag_off + (int64_t)quad * P.nstrips * P.nchunks;
-
-        const int j0 = strip * TY;
-        const int rows = min(TY, ny - j0);
-        T xl[TY];
-#pragma unroll
-        for (int r = 0; r < TY; ++r)
-            xl[r] = (W.xin_off >= 0 && r < rows) ? inflow[W.xin_off + (int64_t)(j0 + r) * kWave + lane] : T(0);
-
-        T* __restrict__ edge_mine = edge + W.edge_off + (int64_t)strip * nx * kWave;
-        const T* __restrict__ edge_below = edge + W.edge_off + (int64_t)(strip - 1) * nx * kWave;
-        long long* prog_mine = A.prog + W.prog_off + strip;
-        long long* prog_below = A.prog + W.prog_off + strip - 1;
-        const bool publish = (strip + 1 < P.nstrips);
-
-        // storage cell of chunk element e = r*TX + i (clamped into the grid for ragged chunks)
-        auto elem_cell = [&](int c, int e, bool& inside) -> int {
-            const int r = e / TX, i = e % TX;
-            int jj = j0 + r, ii = c * TX + i;
-            inside = (jj < ny) && (ii < nx);
-            jj = min(jj, ny - 1);
-            ii = min(ii, nx - 1);
-            const int j = ypos ? jj : ny - 1 - jj;
-            const int is = xpos ? ii : nx - 1 - ii;
-            return j * nx + is;
-        };
-        T pst[PER];
-        T pS[NG > 0 ? NG : 1][PER];
-        // anisotropic sources are per (cell, ordinate): each lane prefetches its own ordinate's
-        // values for the whole next chunk (one coalesced 256-byte load per cell)
-        constexpr int CA = ANG ? CH : 1;
-        T pA[CA], cA[CA];
-        auto prefetch = [&](int c) {
-            if constexpr (ANG) {
-#pragma unroll
-                for (int e = 0; e < CH; ++e) {
-                    bool inside;
-                    const int cell = elem_cell(c, e, inside);
-                    pA[e] = Ap[(int64_t)cell * npad];
-                }
-            }
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int e = lane + k * kWave;
-                if (e < CH) {
-                    bool inside;
-                    const int cell = elem_cell(c, e, inside);
-                    pst[k] = st[cell];
-                    if constexpr (NG > 0) {
-#pragma unroll
-                        for (int q = 0; q < NG; ++q)
-                            if (q < G) pS[q][k] = inside ? sbase[q][cell] : T(0);
-                    }
-                }
-            }
-        };
-        auto commit = [&]() {
-            if constexpr (ANG) {
-#pragma unroll
-                for (int e = 0; e < CH; ++e) cA[e] = pA[e];
-            }
-#pragma unroll
-            for (int k = 0; k < PER; ++k) {
-                const int e = lane + k * kWave;
-                if (e < CH) {
-                    lds_st[e] = pst[k];
-                    if constexpr (NG > 0) {
-#pragma unroll
-                        for (int q = 0; q < NG; ++q)
-                            if (q < G) lds_S[q][e] = pS[q][k];
-                    }
-                }
-            }
-        };
-
-        prefetch(0);
-        for (int c = 0; c < P.nchunks; ++c) {
-            const int i0 = c * TX;
-            const int cols = min(TX, nx - i0);
-            commit();
-            if (c + 1 < P.nchunks) prefetch(c + 1);
-            const int32_t umask = uflags[(int64_t)strip * P.nchunks + c];
-            T yd[TX];
-            if (strip == 0) {
-#pragma unroll
-                for (int i = 0; i < TX; ++i)
-                    yd[i] = (W.yin_off >= 0 && i < cols) ? inflow[W.yin_off + (int64_t)(i0 + i) * kWave + lane] : T(0);
-            } else {
-                wait_progress(prog_below, tag | (long long)(c + 1), A.ctl, A.spin_limit);
-#pragma unroll
-                for (int i = 0; i < TX; ++i)
-                    yd[i] = (i < cols) ? edge_load(edge_below + (int64_t)(i0 + i) * kWave + lane) : T(0);
-            }
-            auto do_row = [&](const int r) {
-                const int jj = j0 + r;
-                const int j = ypos ? jj : ny - 1 - jj;
-                const int64_t rowbase = (int64_t)j * nx;
-                T Sv[TX], acc[TX];
-                if constexpr (ANG) {
-#pragma unroll
-                    for (int i = 0; i < TX; ++i) Sv[i] = cA[r * TX + i];
-                } else {
-#pragma unroll
-                    for (int i = 0; i < TX; ++i) Sv[i] = lds_S[g][r * TX + i];
-                }
-                T xf = xl[r];
-                if ((umask >> r) & 1) {
-                    const T rr = rcp_fast(lds_st[r * TX] + kappa);
-                    const T wr = w * rr, ar = a * rr, br = b * rr;
-#pragma unroll
-                    for (int i = 0; i < TX; ++i) {
-                        const T v = fma(br, yd[i], fma(ar, xf, wr * Sv[i]));
-                        if (DD) {
-                            xf = fma(T(2), v, -xf);
-                            yd[i] = fma(T(2), v, -yd[i]);
-                        } else {
-                            xf = v;
-                            yd[i] = v;
-                        }
-                        acc[i] = v;
-                    }
-                } else {
-#pragma unroll
-                    for (int i = 0; i < TX; ++i) {
-                        const T rr = rcp_fast(lds_st[r * TX + i] + kappa);
-                        const T v = fma(b, yd[i], fma(a, xf, w * Sv[i])) * rr;
-                        if (DD) {
-                            xf = fma(T(2), v, -xf);
-                            yd[i] = fma(T(2), v, -yd[i]);
-                        } else {
-                            xf = v;
-                            yd[i] = v;
-                        }
-                        acc[i] = v;
-                    }
-                }
-                xl[r] = xf;
-                // lanes of empty groups alias ordinate 0 of system sys[0]: they never store
-                if (PSI == 1 && gslot >= 0) {
-                    T* __restrict__ po = (T*)A.psi_out + SD.ang_off + ld.ord;
-#pragma unroll
-                    for (int i = 0; i < TX; ++i) {
-                        const int ii = i0 + i;
-                        if (i < cols) po[(rowbase + (xpos ? ii : nx - 1 - ii)) * npad] = acc[i];
-                    }
-                } else if (PSI == 2 && gslot >= 0) {
-                    __hip_bfloat16* __restrict__ po = (__hip_bfloat16*)A.psi_out + SD.ang_off + ld.ord;
-#pragma unroll
-                    for (int i = 0; i < TX; ++i) {
-                        const int ii = i0 + i;
-                        if (i < cols) po[(rowbase + (xpos ? ii : nx - 1 - ii)) * npad] = __float2bfloat16((float)acc[i]);
-                    }
-                }
-                const RowCtx R{lane, g, L, rowbase, i0, nx, xpos, cols};
-                store_partials<TX>(R, acc, my_part);
-            };
-            if constexpr (ANG || ROM_ROW_UNROLL) {
-#pragma unroll
-                for (int r = 0; r < TY; ++r)
-                    if (r < rows) do_row(r);
-            } else {
-                for (int r = 0; r < rows; ++r) do_row(r);
-            }
-            if (publish) {
-#pragma unroll
-                for (int i = 0; i < TX; ++i)
-                    if (i < cols) edge_store(edge_mine + (int64_t)(i0 + i) * kWave + lane, yd[i]);
-                stores_complete();
-                if (lane == 0)
-                    __hip_atomic_store(prog_mine, tag | (long long)(c + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            }
-        }
-    }
-    if (lane == 0) atomicMax(&A.ctl->t_last, (unsigned long long)wall_clock64());
-}
 
 // ------------------------------------------------------------------------------------ combine
 __device__ __forceinline__ unsigned long long dbits(double x) { return (unsigned long long)__double_as_longlong(x); }
@@ -814,59 +369,43 @@ __global__ void cast_bf16_kernel(const float* __restrict__ in, __hip_bfloat16* _
 }
 
 // ------------------------------------------------------------------------------------ launchers
-template <typename T, int TX, int TY, bool DD, bool ANG, int PSI>
-static hipError_t launch_sweep_t(const SweepArgs& a, int grid, hipStream_t s)
-{
-    hipLaunchKernelGGL((sweep_kernel<T, TX, TY, DD, ANG, PSI>), dim3(grid), dim3(64), 0, s, a);
-    return hipGetLastError();
-}
+hipError_t launch_sweep_f32_8x4(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
+hipError_t launch_sweep_f32_8x8(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
+hipError_t launch_sweep_f32_16x8(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
+hipError_t launch_sweep_f32_16x16(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
+hipError_t launch_sweep_f64_8x4(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
+hipError_t launch_sweep_f64_8x8(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
 
-template <typename T, int TX, int TY>
-static hipError_t launch_sweep_tile(const SweepArgs& a, int grid, bool dd, bool ang, int psi, hipStream_t s)
+size_t sweep_lds_bytes(bool fp64, int tx, int ty, bool ang, int L, int nw)
 {
-    if (dd) {
-        if (ang) {
-            if (psi == 1) return launch_sweep_t<T, TX, TY, true, true, 1>(a, grid, s);
-            if (psi == 2) return launch_sweep_t<T, TX, TY, true, true, 2>(a, grid, s);
-            return launch_sweep_t<T, TX, TY, true, true, 0>(a, grid, s);
-        }
-        if (psi == 1) return launch_sweep_t<T, TX, TY, true, false, 1>(a, grid, s);
-        return launch_sweep_t<T, TX, TY, true, false, 0>(a, grid, s);
-    }
-    if (ang) {
-        if (psi == 1) return launch_sweep_t<T, TX, TY, false, true, 1>(a, grid, s);
-        if (psi == 2) return launch_sweep_t<T, TX, TY, false, true, 2>(a, grid, s);
-        return launch_sweep_t<T, TX, TY, false, true, 0>(a, grid, s);
-    }
-    if (psi == 1) return launch_sweep_t<T, TX, TY, false, false, 1>(a, grid, s);
-    return launch_sweep_t<T, TX, TY, false, false, 0>(a, grid, s);
-}
-
-template <typename T>
-static hipError_t launch_sweep_T(const SweepArgs& a, int grid, int tx, int ty, bool dd, bool ang, int psi,
-                                 hipStream_t s)
-{
-    if (tx == 8 && ty == 4) return launch_sweep_tile<T, 8, 4>(a, grid, dd, ang, psi, s);
-    if (tx == 8 && ty == 8) return launch_sweep_tile<T, 8, 8>(a, grid, dd, ang, psi, s);
-    if (tx == 16 && ty == 4) return launch_sweep_tile<T, 16, 4>(a, grid, dd, ang, psi, s);
-    if (tx == 16 && ty == 8) return launch_sweep_tile<T, 16, 8>(a, grid, dd, ang, psi, s);
-    if (tx == 16 && ty == 16) return launch_sweep_tile<T, 16, 16>(a, grid, dd, ang, psi, s);
-    return hipErrorInvalidValue;
+    const size_t esz = fp64 ? 8 : 4;
+    const size_t ch = (size_t)tx * ty;
+    const size_t ngd = ang ? 1 : (size_t)(kWave / L);
+    return esz * ((size_t)nw * (ch + ngd * (ch + 4)) + (size_t)(nw > 1 ? nw - 1 : 1) * kRingSlots * tx * kWave) +
+           sizeof(int) * (2 * kMaxBand + 1);
 }
 
 bool sweep_tile_supported(int tx, int ty)
 {
-    return (tx == 8 && (ty == 4 || ty == 8)) || (tx == 16 && (ty == 4 || ty == 8 || ty == 16));
+    return (tx == 8 && (ty == 4 || ty == 8)) || (tx == 16 && (ty == 8 || ty == 16));
 }
 
-hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty, bool dd, bool ang, int psi,
+bool sweep_tile_supported_fp64(int tx, int ty) { return tx == 8 && (ty == 4 || ty == 8); }
+
+hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty, bool dd, bool ang, int psi, int L,
                         hipStream_t s)
 {
     if (fp64) {
         if (psi == 2) return hipErrorInvalidValue;
-        return launch_sweep_T<double>(a, grid, tx, ty, dd, ang, psi, s);
+        if (tx == 8 && ty == 4) return launch_sweep_f64_8x4(a, grid, dd, ang, psi, L, s);
+        if (tx == 8 && ty == 8) return launch_sweep_f64_8x8(a, grid, dd, ang, psi, L, s);
+        return hipErrorInvalidValue;
     }
-    return launch_sweep_T<float>(a, grid, tx, ty, dd, ang, psi, s);
+    if (tx == 8 && ty == 4) return launch_sweep_f32_8x4(a, grid, dd, ang, psi, L, s);
+    if (tx == 8 && ty == 8) return launch_sweep_f32_8x8(a, grid, dd, ang, psi, L, s);
+    if (tx == 16 && ty == 8) return launch_sweep_f32_16x8(a, grid, dd, ang, psi, L, s);
+    if (tx == 16 && ty == 16) return launch_sweep_f32_16x16(a, grid, dd, ang, psi, L, s);
+    return hipErrorInvalidValue;
 }
 
 hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s)

@@ -1,0 +1,16 @@
+// rom_sweep_f64.hip -- instantiations of the sweep kernel.
+#include "rom_sweep.h"
+
+namespace rom {
+
+hipError_t launch_sweep_f64_8x4(const SweepArgs& a, int grid, bool dd, bool ang, int psi, int L, hipStream_t s)
+{
+    return launch_sweep_tile<double, 8, 4>(a, grid, dd, ang, psi, L, s);
+}
+
+hipError_t launch_sweep_f64_8x8(const SweepArgs& a, int grid, bool dd, bool ang, int psi, int L, hipStream_t s)
+{
+    return launch_sweep_tile<double, 8, 8>(a, grid, dd, ang, psi, L, s);
+}
+
+}  // namespace rom

@@ -58,7 +58,7 @@ class rom_ord_spec(C.Structure):
 class rom_si_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32), ("scheme", C.c_int32),
                 ("iters_per_check", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
-                ("contract_split", C.c_int32), ("reserved", C.c_int32 * 4)]
+                ("contract_split", C.c_int32), ("band", C.c_int32), ("reserved", C.c_int32 * 3)]
 
 
 class rom_si_stats(C.Structure):
@@ -209,7 +209,7 @@ def _check(st, h=None):
 
 
 def si_opts(tol=1e-6, max_iter=1000, precision=ROM_PREC_FP32, scheme=ROM_SCHEME_STEP, iters_per_check=0,
-            tile=(0, 0), contract_split=0) -> rom_si_opts:
+            tile=(0, 0), contract_split=0, band=0) -> rom_si_opts:
     o = rom_si_opts()
     o.tol = tol
     o.max_iter = max_iter
@@ -218,6 +218,7 @@ def si_opts(tol=1e-6, max_iter=1000, precision=ROM_PREC_FP32, scheme=ROM_SCHEME_
     o.iters_per_check = iters_per_check
     o.tile_x, o.tile_y = tile
     o.contract_split = contract_split
+    o.band = band
     return o
 
 

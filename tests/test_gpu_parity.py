@@ -48,11 +48,12 @@ def both(R, orc, nx, ny, st, ss, q, box=(0.0, 1.0, 0.0, 1.0), inflow=None):
 
 # ------------------------------------------------------------------------------------ single sweep
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
-@pytest.mark.parametrize("tile", [(8, 4), (16, 16), (8, 8)])
+@pytest.mark.parametrize("tile", [(8, 4), (16, 16), (8, 8), (16, 8)])
 @pytest.mark.parametrize("spec", [(2, 4), (8, 8), (1, 3)])
 def test_sweep_isotropic_source(R, orc, prec, tile, spec):
     """One sweep psi = L^{-1} S (shared source) on a ragged 37 x 29 grid with non-square cells,
-    varying cross sections and isotropic inflow on two faces."""
+    varying cross sections and isotropic inflow on two faces.  (FP64 sweeps take 8 x 4 and 8 x 8
+    tiles only; other shapes are refused with ROM_E_ARG.)"""
     rng = np.random.default_rng(11)
     nx, ny = 37, 29
     st, ss, q = rand_problem(rng, nx, ny)
@@ -62,6 +63,11 @@ def test_sweep_isotropic_source(R, orc, prec, tile, spec):
     h.set_ordinates(d, w)
     S = rng.uniform(0.0, 3.0, nx * ny)
     o = R.si_opts(precision=R.ROM_PREC_FP64 if prec == "fp64" else R.ROM_PREC_FP32, tile=tile)
+    if prec == "fp64" and tile[0] != 8:
+        with pytest.raises(R.RomError) as ei:
+            h.sweep(S, o, want_psi=True)
+        assert ei.value.status == R.ROM_E_ARG
+        return
     phi, psi = h.sweep(S, o, want_psi=True)
     psi_ref = orc.sweep(p, d, S)
     phi_ref = orc.scalar_flux(w, psi_ref)
