@@ -125,6 +125,9 @@ typedef struct {
     int32_t status;        /* ROM_OK if every sample converged, else ROM_NOT_CONVERGED */
     int64_t updates;
     double device_ms;
+    double sweep_ms;       /* summed duration of the sweep launches that did work */
+    int32_t sweeps;        /* sweep launches that did work */
+    int32_t pad;
 } rom_ens_stats;
 
 /* ---- lifetime ----------------------------------------------------------------------------- */

@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdlib>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -1087,16 +1088,110 @@ namespace {
 bool is_aniso(const rom_handle* h) { return h->scat != ROM_SCAT_ISO; }
 
 // Source iteration for a list of systems; fills stats and phis.
-int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opts& o, bool cache, std::unique_ptr<Plan>& slot,
-                  SolveResult& res)
+// ------------------------------------------------------------------------------------ autotuner
+//
+// Tile shape (chunk x strip) and band (strips per workgroup) decide the sweep's pipeline depth,
+// per-chunk overhead and occupancy, and the best choice depends on the batch: a single small
+// problem wants short pipelines, a large ensemble wants occupancy.  The first solve of a batch
+// shape times each candidate on the real buffers (one warm-up and two timed sweeps each) and
+// caches the fastest for the process.  Results do not depend on the choice: the cell updates and
+// the lane-reduction tree are the same for every tile and band.
+std::string tune_key(const std::vector<SysInput>& in, const rom_si_opts& o, bool aniso)
+{
+    int maxnx = 0, maxny = 0, maxn = 0;
+    int64_t work = 0;
+    for (auto& s : in) {
+        maxnx = std::max(maxnx, s.h->grid.nx);
+        maxny = std::max(maxny, s.h->grid.ny);
+        maxn = std::max(maxn, s.n);
+        work += s.h->cells * (int64_t)s.n;
+    }
+    char buf[160];
+    std::snprintf(buf, sizeof buf, "p%d s%d a%d k%zu x%d y%d n%d w%lld", o.precision, o.scheme, (int)aniso, in.size(),
+                  maxnx, maxny, maxn, (long long)work);
+    return buf;
+}
+
+bool autotune_enabled()
+{
+    const char* e = std::getenv("ROM_AUTOTUNE");
+    return !(e && e[0] == '0');
+}
+
+void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t s)
+{
+    static std::map<std::string, std::pair<std::pair<int, int>, int>> cache;
+    const std::string key = tune_key(in, o, aniso);
+    auto it = cache.find(key);
+    if (it != cache.end()) {
+        o.tile_x = it->second.first.first;
+        o.tile_y = it->second.first.second;
+        o.band = it->second.second;
+        return;
+    }
+    const bool fp64 = o.precision == ROM_PREC_FP64;
+    std::vector<std::pair<int, int>> tiles = fp64 ? std::vector<std::pair<int, int>>{{8, 4}, {8, 8}}
+                                                  : std::vector<std::pair<int, int>>{{8, 4}, {8, 8}, {16, 8}, {16, 16}};
+    float best = 1e30f;
+    int bx = 0, by = 0, bb = 0;
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    for (auto t : tiles) {
+        for (int band : {2, 4, 8}) {
+            rom_si_opts c = o;
+            c.tile_x = t.first;
+            c.tile_y = t.second;
+            c.band = band;
+            Plan P;
+            try {
+                build_plan(P, in, c, aniso, 1);
+            } catch (const Fail&) {
+                continue;  // band does not fit this tile's LDS
+            }
+            if (P.band != band || sweep_lds_bytes(P.fp64, P.tx, P.ty, aniso, P.L, P.band) > 64 * 1024) continue;
+            int64_t tot = 0;
+            for (auto& sd : P.sys) tot = std::max<int64_t>(tot, sd.phi_off + P.handles[sd.prob]->cells);
+            HIPCHK(launch_fill(P.d_src.p, tot, P.fp64, 0.0, s));
+            if (aniso) HIPCHK(launch_fill(P.d_ang.p, (int64_t)(P.d_ang.bytes / P.esz), P.fp64, 0.0, s));
+            const SweepArgs sa = P.sweep_args(1, 0);
+            float ms = 0.f;
+            for (int rep = 0; rep < 3; ++rep) {
+                HIPCHK(launch_reset_systems(P.d_sysctl.as<SysCtl>(), P.nsys, P.d_ctl.as<Ctl>(), s));
+                if (rep == 1) HIPCHK(hipEventRecord(e0, s));
+                HIPCHK(launch_sweep(sa, P.grid, P.fp64, P.tx, P.ty, P.dd, aniso, aniso ? (P.fp64 ? 1 : 2) : 0, P.L, s));
+            }
+            HIPCHK(hipEventRecord(e1, s));
+            HIPCHK(hipEventSynchronize(e1));
+            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+            Ctl ctl{};
+            HIPCHK(hipMemcpy(&ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost));
+            if (!ctl.error && ms < best) {
+                best = ms;
+                bx = P.tx;
+                by = P.ty;
+                bb = P.band;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (bx == 0) return;  // nothing measurable: keep the heuristic
+    cache[key] = {{bx, by}, bb};
+    o.tile_x = bx;
+    o.tile_y = by;
+    o.band = bb;
+}
+
+int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opts& o_in, bool cache,
+                  std::unique_ptr<Plan>& slot, SolveResult& res)
 {
     const bool aniso = is_aniso(in[0].h);
     for (auto& s : in)
         if (is_aniso(s.h) != aniso) return fail(owner, ROM_E_ARG, "batched problems must all be isotropic or all anisotropic");
-    if (aniso && in.size() > 1 && o.precision == ROM_PREC_FP32) {
-        // every system gets its own contraction launch; nothing else to check
-    }
+    rom_si_opts o = o_in;
     if (!cache || !slot) {
+        if (o.tile_x == 0 && o.band == 0 && autotune_enabled()) autotune(in, o, aniso, owner->stream());
         slot.reset(new Plan());
         build_plan(*slot, in, o, aniso, o.max_iter);
         if (aniso) build_kernel_matrices(*slot, in);
@@ -1185,6 +1280,8 @@ int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, d
                 stats[i].status = sc.state == 1 ? ROM_OK : ROM_NOT_CONVERGED;
                 stats[i].updates = (int64_t)sc.iter * hs[i]->cells * hs[i]->n;
                 stats[i].device_ms = res.ms;
+                stats[i].sweep_ms = res.sweep_ms;
+                stats[i].sweeps = res.sweeps;
             }
             if (sc.state == 3) worst = ROM_E_DIVERGED;
             else if (sc.state != 1 && worst == ROM_OK) worst = ROM_NOT_CONVERGED;
@@ -1229,9 +1326,9 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
             rc = generate_ordinates(*spec, seed, smp, dirs.data() + (size_t)smp * 3 * n, w.data() + (size_t)smp * n);
             if (rc) return fail(h, rc, "ordinate generation failed");
         }
-        int done = 0, min_it = 1 << 30, max_it = 0, worst = ROM_OK;
+        int done = 0, min_it = 1 << 30, max_it = 0, worst = ROM_OK, sweeps = 0;
         int64_t updates = 0;
-        double ms = 0;
+        double ms = 0, sweep_ms = 0;
         std::unique_ptr<Plan> P;
         std::vector<int64_t> offs;
         DevMem d_offs;
@@ -1245,6 +1342,8 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
             rc = solve_systems(h, in, o, false, P, res);
             if (rc) return rc;
             ms += res.ms;
+            sweep_ms += res.sweep_ms;
+            sweeps += res.sweeps;
             offs.assign(b, 0);
             for (int k = 0; k < b; ++k) {
                 offs[k] = P->sys[k].phi_off;
@@ -1282,6 +1381,8 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
             stats->status = worst == ROM_OK ? ROM_OK : ROM_NOT_CONVERGED;
             stats->updates = updates;
             stats->device_ms = ms;
+            stats->sweep_ms = sweep_ms;
+            stats->sweeps = sweeps;
         }
         if (worst == ROM_E_DIVERGED) return fail(h, ROM_E_DIVERGED, "non-finite iterate in a sample");
         return worst;

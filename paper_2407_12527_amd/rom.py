@@ -68,7 +68,8 @@ class rom_si_stats(C.Structure):
 
 class rom_ens_stats(C.Structure):
     _fields_ = [("samples", C.c_int32), ("min_iters", C.c_int32), ("max_iters", C.c_int32), ("status", C.c_int32),
-                ("updates", C.c_int64), ("device_ms", C.c_double)]
+                ("updates", C.c_int64), ("device_ms", C.c_double), ("sweep_ms", C.c_double), ("sweeps", C.c_int32),
+                ("pad", C.c_int32)]
 
 
 def library_path() -> str:
