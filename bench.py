@@ -114,7 +114,7 @@ def bench_batch(a, wl, R, torch):
         R.solve_batch(hs, opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    upd, sweep_ms, sweeps, iters = 0, 0.0, 0, 0
+    upd, sweep_ms, sweeps, iters, shape = 0, 0.0, 0, 0, [0, 0, 0, 0]
     for _ in range(a.steps):
         _, stats, rc = R.solve_batch(hs, opts)
         if rc != 0:
@@ -123,6 +123,7 @@ def bench_batch(a, wl, R, torch):
         sweep_ms += stats[0].sweep_ms
         sweeps += stats[0].sweeps
         iters = max(s.iters for s in stats)
+        shape = [stats[0].tile_x, stats[0].tile_y, stats[0].band, stats[0].lanes]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # Every problem sweeps once per iteration until it converges, so the work of all sweep
@@ -133,7 +134,7 @@ def bench_batch(a, wl, R, torch):
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": DESCR["c5"], "problems": len(hs), "cells": sum(f.cells for f in wl.fields),
-                      "si_iterations": iters},
+                      "si_iterations": iters, "sweep_tile": f"{shape[0]}x{shape[1]}", "band": shape[2]},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "sweep_kernel",
                         "avg_launch_us": avg_s * 1e6, "updates_per_launch": upd / max(sweeps, 1)}}
@@ -198,12 +199,16 @@ def main():
     def step():
         if ens:
             _, _, st, rc = h.ensemble(wl.samples, wl.seed, spec[0], spec[1], spec[2], opts, download=False)
+            shape[:] = [st.tile_x, st.tile_y, st.band, st.lanes]
             return st.updates, st.sweep_ms, st.sweeps, st.max_iters
         h.set_ordinates(dirs, w)                     # ordinate ingestion
         _, st, rc = h.source_iterate(opts, download=False)
         if rc != 0:
             raise RuntimeError(f"solve did not converge (status {rc})")
+        shape[:] = [st.tile_x, st.tile_y, st.band, st.lanes]
         return st.updates, st.sweep_ms, st.sweeps, st.iters
+
+    shape = [0, 0, 0, 0]
 
     for _ in range(a.warmup):
         step()
@@ -243,7 +248,8 @@ def main():
         "dtype": "f64" if fp64 else "f32",
         "data": "synthetic",
         "config": {"workload": DESCR[a.workload], "cells": f.cells, "ordinates": n, "samples": wl.samples,
-                   "si_iterations": iters},
+                   "si_iterations": iters, "sweep_tile": f"{shape[0]}x{shape[1]}", "band": shape[2],
+                   "lanes_per_group": shape[3]},
         "roofline": roof,
     }
     if not a.no_cpu:

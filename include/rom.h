@@ -100,7 +100,9 @@ typedef struct {
     int32_t max_iter;         /* 0 -> 1000 */
     int32_t precision;        /* ROM_PREC_FP32 | ROM_PREC_FP64 */
     int32_t scheme;           /* ROM_SCHEME_STEP | ROM_SCHEME_DD */
-    int32_t iters_per_check;  /* iterations captured per graph replay between host checks; 0 -> auto */
+    int32_t iters_per_check;  /* iterations captured per graph replay between host checks; 0 -> auto
+                                 (the iteration count of the previous solve with the same plan,
+                                 split into replays of at most 64, else 8) */
     int32_t tile_x, tile_y;   /* sweep chunk / strip size in cells; 0 -> autotuned */
     int32_t contract_split;   /* reserved for a split-BF16 contraction; must be 0 */
     int32_t band;             /* consecutive strips per sweep workgroup (1..8); 0 -> automatic */
@@ -116,6 +118,9 @@ typedef struct {
     double sweep_ms;       /* summed duration of the sweep launches that did work, first wave
                               start to last wave end, from the device real-time clock */
     int32_t sweeps;        /* sweep launches that did work */
+    int32_t tile_x, tile_y;/* sweep chunk x strip shape the solve ran with (set or autotuned) */
+    int32_t band;          /* strips per sweep workgroup */
+    int32_t lanes;         /* lanes per ordinate group (16, 32 or 64) */
     int32_t pad;
 } rom_si_stats;
 
@@ -127,6 +132,9 @@ typedef struct {
     double device_ms;
     double sweep_ms;       /* summed duration of the sweep launches that did work */
     int32_t sweeps;        /* sweep launches that did work */
+    int32_t tile_x, tile_y;/* sweep shape of the last batch of samples */
+    int32_t band;
+    int32_t lanes;
     int32_t pad;
 } rom_ens_stats;
 

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <array>
+#include <atomic>
 #include <chrono>
 #include <cstdlib>
 #include <cmath>
@@ -81,6 +83,15 @@ void upload(DevMem& d, const std::vector<T>& v)
     if (!v.empty()) HIPCHK(hipMemcpy(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice));
 }
 
+// Overwrite an existing allocation of exactly the same size (its address stays valid for a
+// captured graph); stream-ordered after the work already queued on s.
+template <typename T>
+void rewrite(DevMem& d, const std::vector<T>& v, hipStream_t s)
+{
+    if (d.bytes < v.size() * sizeof(T) || (!v.empty() && !d.p)) throw Fail{ROM_E_STATE, "plan table size changed"};
+    if (!v.empty()) HIPCHK(hipMemcpyAsync(d.p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+}
+
 uint16_t f32_to_bf16(float f)
 {
     uint32_t u;
@@ -118,10 +129,20 @@ struct rom_handle {
     std::unique_ptr<Plan> plan;
     uint64_t plan_version = 0;
     std::string plan_sig;
+    // plans of the last ensemble and of the last batch led by this handle, kept for reuse
+    std::unique_ptr<Plan> ens_plan, batch_plan;
+    std::string ens_key, batch_key, batch_versions;
+    uint64_t uid = next_uid();
     // device-resident result of the last solve
     const void* res_dev = nullptr;
     bool res_fp64 = false;
     DevMem ens_mean, ens_m2, ens_var;
+
+    static uint64_t next_uid()
+    {
+        static std::atomic<uint64_t> counter{0};
+        return ++counter;
+    }
 
     hipStream_t stream()
     {
@@ -174,6 +195,12 @@ struct Plan {
     std::vector<int> sys_n;                 // per system: real ordinate count
     std::vector<const double*> sys_w;       // per system: caller weights
     std::vector<int> npad_al;               // per system: padded stride of the anisotropic layout
+    std::vector<std::array<int, 4>> qcount;  // per system: ordinates per quadrant
+    int64_t inflow_len = 0;                 // elements of the weighted inflow table (0: vacuum)
+    std::vector<double> h_inflow;           // host copies kept for stream-ordered rewrites
+    std::vector<float> h_inflow32;
+    std::vector<double> h_bt64;
+    std::vector<uint16_t> h_bt16;
     int cells_per_block = 1024;
 
     DevMem d_probs, d_sys, d_ws, d_lanes, d_tickets, d_slot_off, d_slot_order, d_cblocks;
@@ -183,6 +210,7 @@ struct Plan {
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
     int graph_iters = 0;
+    int last_iters = 0;   // largest iteration count of the previous solve with this plan
     double graph_tol = 0.0;
     hipStream_t graph_stream = nullptr;
 
@@ -311,6 +339,45 @@ void choose_tiles(const rom_si_opts& o, const std::vector<SysInput>& in, bool fp
 }
 
 // Build every table and buffer of a plan for the given systems.
+// Boundary inflow of every wave-stream lane in sweep order, scaled by the lane's weight.
+std::vector<double> inflow_table(const Plan& P, const std::vector<SysInput>& in)
+{
+    std::vector<double> inf(P.inflow_len, 0.0);
+    for (int k = 0; k < P.nws; ++k) {
+        const WaveStreamDev& W = P.ws[k];
+        if (W.xin_off < 0) continue;
+        rom_handle* h = P.handles[W.prob];
+        const int nx = h->grid.nx, ny = h->grid.ny;
+        const bool xpos = (W.quad == 0 || W.quad == 3), ypos = (W.quad < 2);
+        const int fx = xpos ? ROM_FACE_LEFT : ROM_FACE_RIGHT;
+        const int fy = ypos ? ROM_FACE_BOTTOM : ROM_FACE_TOP;
+        for (int lane = 0; lane < kWave; ++lane) {
+            const int gi = lane / W.L;
+            const int s = W.sys[gi];
+            if (s < 0) continue;
+            const LaneDev& ld = P.lanes[(size_t)k * kWave + lane];
+            const int u = P.user_of[s][ld.ord];
+            if (u < 0) continue;
+            const bool angok = in[s].use_angular;
+            for (int jj = 0; jj < ny; ++jj) {
+                const int j = ypos ? jj : ny - 1 - jj;
+                double v = 0.0;
+                if (angok && !h->ang[fx].empty()) v = h->ang[fx][(size_t)u * ny + j];
+                else if (!h->face[fx].empty()) v = h->face[fx][j];
+                inf[W.xin_off + (int64_t)jj * kWave + lane] = ld.w * v;
+            }
+            for (int ii = 0; ii < nx; ++ii) {
+                const int i = xpos ? ii : nx - 1 - ii;
+                double v = 0.0;
+                if (angok && !h->ang[fy].empty()) v = h->ang[fy][(size_t)u * nx + i];
+                else if (!h->face[fy].empty()) v = h->face[fy][i];
+                inf[W.yin_off + (int64_t)ii * kWave + lane] = ld.w * v;
+            }
+        }
+    }
+    return inf;
+}
+
 void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, bool aniso, int max_iter,
                 bool psi_out = false)
 {
@@ -388,10 +455,12 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     };
     std::vector<QuadList> ql(in.size());
     int Lb = (aniso || psi_out) ? 64 : 16;
+    P.qcount.assign(in.size(), {0, 0, 0, 0});
     for (size_t k = 0; k < in.size(); ++k) {
         for (int l = 0; l < in[k].n; ++l) ql[k].idx[quadrant_of(in[k].dirs[3 * l], in[k].dirs[3 * l + 1])].push_back(l);
         for (int q = 0; q < 4; ++q) {
             const int m = (int)ql[k].idx[q].size();
+            P.qcount[k][q] = m;
             while (Lb < 64 && Lb < m) Lb *= 2;
         }
     }
@@ -578,40 +647,9 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     cast_upload(P.d_q, qv);
 
     // inflow in sweep order, scaled by the lane weight
+    P.inflow_len = inflow_sum;
     if (inflow_sum > 0) {
-        std::vector<double> inf(inflow_sum, 0.0);
-        for (int k = 0; k < P.nws; ++k) {
-            const WaveStreamDev& W = P.ws[k];
-            if (W.xin_off < 0) continue;
-            rom_handle* h = P.handles[W.prob];
-            const int nx = h->grid.nx, ny = h->grid.ny;
-            const bool xpos = (W.quad == 0 || W.quad == 3), ypos = (W.quad < 2);
-            const int fx = xpos ? ROM_FACE_LEFT : ROM_FACE_RIGHT;
-            const int fy = ypos ? ROM_FACE_BOTTOM : ROM_FACE_TOP;
-            for (int lane = 0; lane < kWave; ++lane) {
-                const int gi = lane / W.L;
-                const int s = W.sys[gi];
-                if (s < 0) continue;
-                const LaneDev& ld = P.lanes[(size_t)k * kWave + lane];
-                const int u = P.user_of[s][ld.ord];
-                if (u < 0) continue;
-                const bool angok = in[s].use_angular;
-                for (int jj = 0; jj < ny; ++jj) {
-                    const int j = ypos ? jj : ny - 1 - jj;
-                    double v = 0.0;
-                    if (angok && !h->ang[fx].empty()) v = h->ang[fx][(size_t)u * ny + j];
-                    else if (!h->face[fx].empty()) v = h->face[fx][j];
-                    inf[W.xin_off + (int64_t)jj * kWave + lane] = ld.w * v;
-                }
-                for (int ii = 0; ii < nx; ++ii) {
-                    const int i = xpos ? ii : nx - 1 - ii;
-                    double v = 0.0;
-                    if (angok && !h->ang[fy].empty()) v = h->ang[fy][(size_t)u * nx + i];
-                    else if (!h->face[fy].empty()) v = h->face[fy][i];
-                    inf[W.yin_off + (int64_t)ii * kWave + lane] = ld.w * v;
-                }
-            }
-        }
+        const std::vector<double> inf = inflow_table(P, in);
         cast_upload(P.d_inflow, inf);
     } else {
         HIPCHK(P.d_inflow.alloc(256));
@@ -635,7 +673,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
 }
 
 // P^T in internal order for every system: Bt[n][k] = P(u_k, u_n), zero on padding.
-void build_kernel_matrices(Plan& P, const std::vector<SysInput>& in)
+void build_kernel_matrices(Plan& P, const std::vector<SysInput>& in, hipStream_t rewrite_on = nullptr)
 {
     int64_t total = 0;
     P.pt_off.resize(P.nsys);
@@ -643,8 +681,8 @@ void build_kernel_matrices(Plan& P, const std::vector<SysInput>& in)
         P.pt_off[s] = total;
         total += (int64_t)P.npad_al[s] * P.npad_al[s];
     }
-    std::vector<double> bt64;
-    std::vector<uint16_t> bt16;
+    std::vector<double>& bt64 = P.h_bt64;
+    std::vector<uint16_t>& bt16 = P.h_bt16;
     if (P.fp64) bt64.assign(total, 0.0);
     else bt16.assign(total, 0);
     for (int s = 0; s < P.nsys; ++s) {
@@ -667,8 +705,82 @@ void build_kernel_matrices(Plan& P, const std::vector<SysInput>& in)
             }
         }
     }
-    if (P.fp64) upload(P.d_Pt, bt64);
-    else upload(P.d_Pt, bt16);
+    if (rewrite_on) {
+        if (P.fp64) rewrite(P.d_Pt, bt64, rewrite_on);
+        else rewrite(P.d_Pt, bt16, rewrite_on);
+    } else {
+        if (P.fp64) upload(P.d_Pt, bt64);
+        else upload(P.d_Pt, bt16);
+    }
+}
+
+// New ordinate values (and inflow or kernel values) for a plan whose structure still fits: the
+// same systems, the same ordinate count in every quadrant and the same inflow presence.  Rewrites
+// the lane table, the weighted inflow and the kernel matrices in place, stream-ordered on s, so
+// buffers and the captured graph stay valid.  Returns false when the plan must be rebuilt.
+bool refresh_ordinates(Plan& P, const std::vector<SysInput>& in, hipStream_t s)
+{
+    if ((int)in.size() != P.nsys) return false;
+    std::vector<std::array<std::vector<int>, 4>> ql(in.size());
+    for (size_t k = 0; k < in.size(); ++k) {
+        if (in[k].h != P.handles[P.sys[k].prob]) return false;
+        for (int l = 0; l < in[k].n; ++l) ql[k][quadrant_of(in[k].dirs[3 * l], in[k].dirs[3 * l + 1])].push_back(l);
+        for (int q = 0; q < 4; ++q)
+            if ((int)ql[k][q].size() != P.qcount[k][q]) return false;
+    }
+    for (int p = 0; p < (int)P.handles.size(); ++p) {
+        rom_handle* h = P.handles[p];
+        bool vacuum = true;
+        for (int f = 0; f < 4; ++f)
+            if (!h->face[f].empty()) vacuum = false;
+        for (auto& si : in)
+            if (si.h == h && si.use_angular)
+                for (int f = 0; f < 4; ++f)
+                    if (!h->ang[f].empty()) vacuum = false;
+        const bool had = P.inflow_len > 0;
+        if (!vacuum != had) return false;
+    }
+    // internal order: quadrant-major, L-lane groups, padded (as built)
+    for (int k = 0; k < P.nsys; ++k) {
+        std::vector<int>& uo = P.user_of[k];
+        const size_t before = uo.size();
+        uo.clear();
+        for (int q = 0; q < 4; ++q) {
+            const auto& list = ql[k][q];
+            for (size_t b = 0; b < list.size(); b += P.L)
+                for (int l = 0; l < P.L; ++l) uo.push_back(b + l < list.size() ? list[b + l] : -1);
+        }
+        if (uo.size() != before) throw Fail{ROM_E_STATE, "ordinate layout changed"};
+        P.sys_n[k] = in[k].n;
+        P.sys_w[k] = in[k].w;
+    }
+    for (int k = 0; k < P.nws; ++k) {
+        const WaveStreamDev& W = P.ws[k];
+        rom_handle* h = P.handles[W.prob];
+        for (int lane = 0; lane < kWave; ++lane) {
+            LaneDev& ld = P.lanes[(size_t)k * kWave + lane];
+            const int sy = W.sys[lane / W.L];
+            ld.a = ld.b = ld.w = 0.0;
+            if (sy < 0) continue;
+            const int u = P.user_of[sy][ld.ord];
+            if (u < 0) continue;
+            ld.a = std::fabs(in[sy].dirs[3 * u]) / h->dx;
+            ld.b = std::fabs(in[sy].dirs[3 * u + 1]) / h->dy;
+            ld.w = in[sy].w[u];
+        }
+    }
+    rewrite(P.d_lanes, P.lanes, s);
+    if (P.inflow_len > 0) {
+        P.h_inflow = inflow_table(P, in);
+        if (P.fp64) {
+            rewrite(P.d_inflow, P.h_inflow, s);
+        } else {
+            P.h_inflow32.assign(P.h_inflow.begin(), P.h_inflow.end());
+            rewrite(P.d_inflow, P.h_inflow32, s);
+        }
+    }
+    if (P.aniso) build_kernel_matrices(P, in, s);
+    return true;
 }
 
 void enqueue_iteration(Plan& P, hipStream_t s, double tol)
@@ -701,6 +813,7 @@ struct SolveResult {
     double ms = 0;
     double sweep_ms = 0;
     int sweeps = 0;
+    int tx = 0, ty = 0, band = 0, lanes = 0;
 };
 
 // Source iteration for every system of the plan.  The first iterate starts from phi = 0 (so the
@@ -709,7 +822,13 @@ struct SolveResult {
 SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
 {
     const double tol = o.tol;
+    // Iterations per replay: by default the previous solve's count (split into replays of at most
+    // 64), so a repeated solve of the same shape launches no iterations past convergence.
     int K = o.iters_per_check > 0 ? o.iters_per_check : 0;
+    if (K == 0 && P.last_iters > 0) {
+        const int reps = (P.last_iters + 63) / 64;
+        K = (P.last_iters + reps - 1) / reps;
+    }
     if (K == 0) K = P.max_iter <= 64 ? 4 : 8;
     K = std::min(K, P.max_iter);
     hipEvent_t e0, e1;
@@ -779,6 +898,13 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     r.sweeps = ctl.sweeps;
     r.sc.resize(P.nsys);
     HIPCHK(hipMemcpy(r.sc.data(), P.d_sysctl.p, P.nsys * sizeof(SysCtl), hipMemcpyDeviceToHost));
+    int most = 0;
+    for (const SysCtl& c : r.sc) most = std::max(most, c.iter);
+    P.last_iters = most;
+    r.tx = P.tx;
+    r.ty = P.ty;
+    r.band = P.band;
+    r.lanes = P.L;
     return r;
 }
 
@@ -1183,14 +1309,17 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t
     o.band = bb;
 }
 
-int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opts& o_in, bool cache,
+// reuse: 0 build a new plan, 1 run the cached plan as it is, 2 refresh its ordinate tables first
+// (rebuilding when the structure no longer fits)
+int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opts& o_in, int reuse,
                   std::unique_ptr<Plan>& slot, SolveResult& res)
 {
     const bool aniso = is_aniso(in[0].h);
     for (auto& s : in)
         if (is_aniso(s.h) != aniso) return fail(owner, ROM_E_ARG, "batched problems must all be isotropic or all anisotropic");
     rom_si_opts o = o_in;
-    if (!cache || !slot) {
+    if (reuse == 2 && slot && !refresh_ordinates(*slot, in, owner->stream())) reuse = 0;
+    if (reuse == 0 || !slot) {
         if (o.tile_x == 0 && o.band == 0 && autotune_enabled()) autotune(in, o, aniso, owner->stream());
         slot.reset(new Plan());
         build_plan(*slot, in, o, aniso, o.max_iter);
@@ -1215,7 +1344,7 @@ int rom_source_iterate(rom_handle* h, const rom_si_opts* opts, double* phi, rom_
     try {
         std::vector<SysInput> in{{h, h->dirs.data(), h->w.data(), h->n, true}};
         const std::string sig = plan_signature(o, is_aniso(h), 0, 1);
-        const bool reuse = h->plan && h->plan_version == h->version && h->plan_sig == sig;
+        const int reuse = !(h->plan && h->plan_sig == sig) ? 0 : h->plan_version == h->version ? 1 : 2;
         if (!reuse) h->plan.reset();
         SolveResult res;
         rc = solve_systems(h, in, o, reuse, h->plan, res);
@@ -1235,6 +1364,10 @@ int rom_source_iterate(rom_handle* h, const rom_si_opts* opts, double* phi, rom_
             stats->device_ms = res.ms;
             stats->sweep_ms = res.sweep_ms;
             stats->sweeps = res.sweeps;
+            stats->tile_x = res.tx;
+            stats->tile_y = res.ty;
+            stats->band = res.band;
+            stats->lanes = res.lanes;
         }
         if (sc.state == 3) return fail(h, ROM_E_DIVERGED, "non-finite iterate");
         return sc.state == 1 ? ROM_OK : ROM_NOT_CONVERGED;
@@ -1266,10 +1399,22 @@ int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, d
     try {
         std::vector<SysInput> in;
         for (int i = 0; i < k; ++i) in.push_back({hs[i], hs[i]->dirs.data(), hs[i]->w.data(), hs[i]->n, true});
-        std::unique_ptr<Plan> P;
+        // the batch plan is reused for the same handles in the same order (refreshed if any of
+        // them changed ordinates, inflow or kernel since)
+        std::string key = plan_signature(o, is_aniso(h0), 1, k), vers;
+        for (int i = 0; i < k; ++i) {
+            key += " " + std::to_string(hs[i]->uid);
+            vers += " " + std::to_string(hs[i]->version);
+        }
+        std::unique_ptr<Plan>& P = h0->batch_plan;
+        const int reuse = !(P && h0->batch_key == key) ? 0 : h0->batch_versions == vers ? 1 : 2;
+        if (!reuse) P.reset();
+        h0->batch_key.clear();
         SolveResult res;
-        rc = solve_systems(h0, in, o, false, P, res);
+        rc = solve_systems(h0, in, o, reuse, P, res);
         if (rc) return rc;
+        h0->batch_key = key;
+        h0->batch_versions = vers;
         int worst = ROM_OK;
         for (int i = 0; i < k; ++i) {
             const SysCtl& sc = res.sc[i];
@@ -1282,13 +1427,14 @@ int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, d
                 stats[i].device_ms = res.ms;
                 stats[i].sweep_ms = res.sweep_ms;
                 stats[i].sweeps = res.sweeps;
+                stats[i].tile_x = res.tx;
+                stats[i].tile_y = res.ty;
+                stats[i].band = res.band;
+                stats[i].lanes = res.lanes;
             }
             if (sc.state == 3) worst = ROM_E_DIVERGED;
             else if (sc.state != 1 && worst == ROM_OK) worst = ROM_NOT_CONVERGED;
         }
-        // keep the batch plan alive on the first handle so its device results stay readable
-        h0->plan = std::move(P);
-        h0->plan_version = 0;
         h0->res_dev = nullptr;
         return worst;
     } catch (const Fail& f) {
@@ -1329,7 +1475,9 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
         int done = 0, min_it = 1 << 30, max_it = 0, worst = ROM_OK, sweeps = 0;
         int64_t updates = 0;
         double ms = 0, sweep_ms = 0;
-        std::unique_ptr<Plan> P;
+        int shape[4] = {0, 0, 0, 0};
+        // one plan per batch shape, refreshed with each batch's ordinates
+        std::unique_ptr<Plan>& P = h->ens_plan;
         std::vector<int64_t> offs;
         DevMem d_offs;
         while (done < t) {
@@ -1337,13 +1485,23 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
             std::vector<SysInput> in;
             for (int k = 0; k < b; ++k)
                 in.push_back({h, dirs.data() + (size_t)(done + k) * 3 * n, w.data() + (size_t)(done + k) * n, n, false});
+            char kb[96];
+            std::snprintf(kb, sizeof kb, " e%d %d %d %d", spec->kind, n, b, h->scat);
+            const std::string key = plan_signature(o, aniso, 2, b) + kb;
+            const int reuse = (P && h->ens_key == key) ? 2 : 0;
+            if (!reuse) P.reset();
+            h->ens_key.clear();
             SolveResult res;
-            P.reset();
-            rc = solve_systems(h, in, o, false, P, res);
+            rc = solve_systems(h, in, o, reuse, P, res);
             if (rc) return rc;
+            h->ens_key = key;
             ms += res.ms;
             sweep_ms += res.sweep_ms;
             sweeps += res.sweeps;
+            shape[0] = res.tx;
+            shape[1] = res.ty;
+            shape[2] = res.band;
+            shape[3] = res.lanes;
             offs.assign(b, 0);
             for (int k = 0; k < b; ++k) {
                 offs[k] = P->sys[k].phi_off;
@@ -1370,8 +1528,6 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
         HIPCHK(hipStreamSynchronize(s));
         if (mean) HIPCHK(hipMemcpy(mean, h->ens_mean.p, h->cells * 8, hipMemcpyDeviceToHost));
         if (var) HIPCHK(hipMemcpy(var, h->ens_var.p, h->cells * 8, hipMemcpyDeviceToHost));
-        h->plan = std::move(P);
-        h->plan_version = 0;
         h->res_dev = h->ens_mean.p;
         h->res_fp64 = true;
         if (stats) {
@@ -1383,6 +1539,10 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
             stats->device_ms = ms;
             stats->sweep_ms = sweep_ms;
             stats->sweeps = sweeps;
+            stats->tile_x = shape[0];
+            stats->tile_y = shape[1];
+            stats->band = shape[2];
+            stats->lanes = shape[3];
         }
         if (worst == ROM_E_DIVERGED) return fail(h, ROM_E_DIVERGED, "non-finite iterate in a sample");
         return worst;

@@ -63,12 +63,14 @@ class rom_si_opts(C.Structure):
 
 class rom_si_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("final_r", C.c_double), ("updates", C.c_int64),
-                ("device_ms", C.c_double), ("sweep_ms", C.c_double), ("sweeps", C.c_int32), ("pad", C.c_int32)]
+                ("device_ms", C.c_double), ("sweep_ms", C.c_double), ("sweeps", C.c_int32), ("tile_x", C.c_int32),
+                ("tile_y", C.c_int32), ("band", C.c_int32), ("lanes", C.c_int32), ("pad", C.c_int32)]
 
 
 class rom_ens_stats(C.Structure):
     _fields_ = [("samples", C.c_int32), ("min_iters", C.c_int32), ("max_iters", C.c_int32), ("status", C.c_int32),
                 ("updates", C.c_int64), ("device_ms", C.c_double), ("sweep_ms", C.c_double), ("sweeps", C.c_int32),
+                ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("band", C.c_int32), ("lanes", C.c_int32),
                 ("pad", C.c_int32)]
 
 
