@@ -55,6 +55,14 @@ def parse():
     return ap.parse_args()
 
 
+def sweep_shape(shape):
+    """The sweep kernel and shape a solve ran with (as rom_si_stats reports them)."""
+    tx, ty, band, lanes, kind = shape
+    if kind == 2:
+        return {"sweep_kernel": "row-lane", "rows_per_block": ty, "ordinates_per_lane": tx, "waves_per_group": band}
+    return {"sweep_kernel": "strip", "sweep_tile": f"{tx}x{ty}", "band": band, "lanes_per_group": lanes}
+
+
 def calibrate_copy(nbytes):
     """A plain copy kernel of known size: its FETCH_SIZE / WRITE_SIZE counters give the scale
     factor between the counters and bytes moved."""
@@ -114,7 +122,7 @@ def bench_batch(a, wl, R, torch):
         R.solve_batch(hs, opts)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    upd, sweep_ms, sweeps, iters, shape = 0, 0.0, 0, 0, [0, 0, 0, 0]
+    upd, sweep_ms, sweeps, iters, shape = 0, 0.0, 0, 0, [0, 0, 0, 0, 0]
     for _ in range(a.steps):
         _, stats, rc = R.solve_batch(hs, opts)
         if rc != 0:
@@ -123,7 +131,7 @@ def bench_batch(a, wl, R, torch):
         sweep_ms += stats[0].sweep_ms
         sweeps += stats[0].sweeps
         iters = max(s.iters for s in stats)
-        shape = [stats[0].tile_x, stats[0].tile_y, stats[0].band, stats[0].lanes]
+        shape = [stats[0].tile_x, stats[0].tile_y, stats[0].band, stats[0].lanes, stats[0].sweep]
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     # Every problem sweeps once per iteration until it converges, so the work of all sweep
@@ -134,7 +142,7 @@ def bench_batch(a, wl, R, torch):
            "steps": a.steps, "warmup": a.warmup, "ms_per_step": dt / a.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": DESCR["c5"], "problems": len(hs), "cells": sum(f.cells for f in wl.fields),
-                      "si_iterations": iters, "sweep_tile": f"{shape[0]}x{shape[1]}", "band": shape[2]},
+                      "si_iterations": iters, **sweep_shape(shape)},
            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "sweep_kernel",
                         "avg_launch_us": avg_s * 1e6, "updates_per_launch": upd / max(sweeps, 1)}}
@@ -199,16 +207,16 @@ def main():
     def step():
         if ens:
             _, _, st, rc = h.ensemble(wl.samples, wl.seed, spec[0], spec[1], spec[2], opts, download=False)
-            shape[:] = [st.tile_x, st.tile_y, st.band, st.lanes]
+            shape[:] = [st.tile_x, st.tile_y, st.band, st.lanes, st.sweep]
             return st.updates, st.sweep_ms, st.sweeps, st.max_iters
         h.set_ordinates(dirs, w)                     # ordinate ingestion
         _, st, rc = h.source_iterate(opts, download=False)
         if rc != 0:
             raise RuntimeError(f"solve did not converge (status {rc})")
-        shape[:] = [st.tile_x, st.tile_y, st.band, st.lanes]
+        shape[:] = [st.tile_x, st.tile_y, st.band, st.lanes, st.sweep]
         return st.updates, st.sweep_ms, st.sweeps, st.iters
 
-    shape = [0, 0, 0, 0]
+    shape = [0, 0, 0, 0, 0]
 
     for _ in range(a.warmup):
         step()
@@ -248,8 +256,7 @@ def main():
         "dtype": "f64" if fp64 else "f32",
         "data": "synthetic",
         "config": {"workload": DESCR[a.workload], "cells": f.cells, "ordinates": n, "samples": wl.samples,
-                   "si_iterations": iters, "sweep_tile": f"{shape[0]}x{shape[1]}", "band": shape[2],
-                   "lanes_per_group": shape[3]},
+                   "si_iterations": iters, **sweep_shape(shape)},
         "roofline": roof,
     }
     if not a.no_cpu:

@@ -65,6 +65,14 @@ extern "C" {
 #define ROM_PREC_FP32 0 /* sweeps in FP32; residual and moments in FP64 */
 #define ROM_PREC_FP64 1 /* everything in FP64 (plain DOM arm) */
 
+/* Sweep kernels.  STRIP: ordinates on lanes, strips of cells handed from wavefront to wavefront
+ * (every scheme, source kind and angular-flux output).  DIAG: grid rows on lanes, each
+ * wavefront sweeping the anti-diagonals of a 16- or 64-row block with the y-face value passed one
+ * lane up; far more parallel work per ordinate, for isotropic step-scheme source iteration. */
+#define ROM_SWEEP_AUTO 0
+#define ROM_SWEEP_STRIP 1
+#define ROM_SWEEP_DIAG 2
+
 #define ROM_FACE_LEFT 0
 #define ROM_FACE_RIGHT 1
 #define ROM_FACE_BOTTOM 2
@@ -105,8 +113,11 @@ typedef struct {
                                  split into replays of at most 64, else 8) */
     int32_t tile_x, tile_y;   /* sweep chunk / strip size in cells; 0 -> autotuned */
     int32_t contract_split;   /* reserved for a split-BF16 contraction; must be 0 */
-    int32_t band;             /* consecutive strips per sweep workgroup (1..8); 0 -> automatic */
-    int32_t reserved[3];
+    int32_t band;             /* strip sweep: consecutive strips per workgroup (1..8); row-lane
+                                 sweep: wavefronts per workgroup (1..16); 0 -> automatic */
+    int32_t sweep;            /* ROM_SWEEP_AUTO (0), ROM_SWEEP_STRIP or ROM_SWEEP_DIAG */
+    int32_t diag_rows;        /* row-lane sweep: grid rows per lane block, 16 or 64; 0 -> automatic */
+    int32_t diag_k;           /* row-lane sweep: ordinates per lane, 1, 2 or 4 (FP64: 1, 2); 0 -> automatic */
 } rom_si_opts;
 
 typedef struct {
@@ -118,10 +129,11 @@ typedef struct {
     double sweep_ms;       /* summed duration of the sweep launches that did work, first wave
                               start to last wave end, from the device real-time clock */
     int32_t sweeps;        /* sweep launches that did work */
-    int32_t tile_x, tile_y;/* sweep chunk x strip shape the solve ran with (set or autotuned) */
-    int32_t band;          /* strips per sweep workgroup */
-    int32_t lanes;         /* lanes per ordinate group (16, 32 or 64) */
-    int32_t pad;
+    int32_t tile_x, tile_y;/* strip sweep: chunk x strip shape; row-lane sweep: ordinates per lane
+                              and rows per lane block (set or autotuned) */
+    int32_t band;          /* strips (strip sweep) or wavefronts (row-lane sweep) per workgroup */
+    int32_t lanes;         /* strip sweep: lanes per ordinate group (16, 32 or 64) */
+    int32_t sweep;         /* ROM_SWEEP_STRIP or ROM_SWEEP_DIAG */
 } rom_si_stats;
 
 typedef struct {
@@ -132,10 +144,10 @@ typedef struct {
     double device_ms;
     double sweep_ms;       /* summed duration of the sweep launches that did work */
     int32_t sweeps;        /* sweep launches that did work */
-    int32_t tile_x, tile_y;/* sweep shape of the last batch of samples */
+    int32_t tile_x, tile_y;/* sweep shape of the last batch of samples (as in rom_si_stats) */
     int32_t band;
     int32_t lanes;
-    int32_t pad;
+    int32_t sweep;
 } rom_ens_stats;
 
 /* ---- lifetime ----------------------------------------------------------------------------- */

@@ -202,6 +202,11 @@ struct Plan {
     std::vector<double> h_bt64;
     std::vector<uint16_t> h_bt16;
     int cells_per_block = 1024;
+    // row-lane sweep
+    int kind = ROM_SWEEP_STRIP;
+    int dR = 16, dK = 1, dNB = 1, wrap_cols = 0;
+    std::vector<DiagTaskDev> dtasks;
+    DevMem d_dtasks;
 
     DevMem d_probs, d_sys, d_ws, d_lanes, d_tickets, d_slot_off, d_slot_order, d_cblocks;
     DevMem d_st, d_ss, d_q, d_src, d_phi, d_part, d_edge, d_inflow, d_prog, d_ctl, d_sysctl, d_rhist;
@@ -220,6 +225,37 @@ struct Plan {
         if (graph) (void)hipGraphDestroy(graph);
     }
 
+    // the sigma_t and source pools carry kPoolPad elements of padding on both sides
+    char* st_ptr() const { return (char*)d_st.p + (size_t)kPoolPad * esz; }
+    char* src_ptr() const { return (char*)d_src.p + (size_t)kPoolPad * esz; }
+
+    DiagArgs diag_args(int mode_all) const
+    {
+        DiagArgs a{};
+        a.tasks = d_dtasks.as<DiagTaskDev>();
+        a.ords = d_lanes.as<LaneDev>();
+        a.probs = d_probs.as<ProblemDev>();
+        a.sys = d_sys.as<SystemDev>();
+        a.spin_limit = 1 << 24;
+        a.mode_all = mode_all;
+        a.wrap_cols = wrap_cols;
+        a.sigma_t = st_ptr();
+        a.src = src_ptr();
+        a.part = d_part.p;
+        a.slot_off = d_slot_off.as<int64_t>();
+        a.inflow = d_inflow.p;
+        a.ctl = d_ctl.as<Ctl>();
+        a.sysctl = d_sysctl.as<SysCtl>();
+        return a;
+    }
+
+    // one sweep of every running system, with the plan's kernel
+    hipError_t launch_sweep_any(int mode_all, hipStream_t s) const
+    {
+        if (kind == ROM_SWEEP_DIAG) return launch_diag(diag_args(mode_all), (int)dtasks.size(), dNB, fp64, dR, dK, s);
+        return launch_sweep(sweep_args(mode_all, 0), grid, fp64, tx, ty, dd, aniso, aniso ? (fp64 ? 1 : 2) : 0, L, s);
+    }
+
     SweepArgs sweep_args(int mode_all, int psi_mode) const
     {
         SweepArgs a{};
@@ -232,8 +268,8 @@ struct Plan {
         a.spin_limit = 1 << 24;
         a.mode_all = mode_all;
         a.band = band;
-        a.sigma_t = d_st.p;
-        a.src = d_src.p;
+        a.sigma_t = st_ptr();
+        a.src = src_ptr();
         a.ang_src = d_ang.p;
         a.psi_out = d_psi.p;
         a.part = d_part.p;
@@ -263,7 +299,7 @@ struct Plan {
         c.tol = tol;
         c.part = d_part.p;
         c.phi = d_phi.p;
-        c.src = d_src.p;
+        c.src = src_ptr();
         c.sigma_s = d_ss.p;
         c.q = d_q.p;
         c.sysctl = d_sysctl.as<SysCtl>();
@@ -339,6 +375,56 @@ void choose_tiles(const rom_si_opts& o, const std::vector<SysInput>& in, bool fp
 }
 
 // Build every table and buffer of a plan for the given systems.
+// True when a problem of the batch has any boundary inflow (isotropic, or angular for a system
+// that takes the handle's angular inflow).
+bool has_inflow(rom_handle* h, const std::vector<SysInput>& in)
+{
+    for (int f = 0; f < 4; ++f)
+        if (!h->face[f].empty()) return true;
+    for (auto& s : in)
+        if (s.h == h && s.use_angular)
+            for (int f = 0; f < 4; ++f)
+                if (!h->ang[f].empty()) return true;
+    return false;
+}
+
+// Row-lane sweep: unweighted inflow of every task ordinate on its entry faces, rows (x-face)
+// and columns (y-face) in sweep order, [position][NO].
+std::vector<double> diag_inflow_table(const Plan& P, const std::vector<SysInput>& in)
+{
+    const int NO = (kWave / P.dR) * P.dK;
+    std::vector<double> inf(P.inflow_len, 0.0);
+    for (const DiagTaskDev& t : P.dtasks) {
+        if (t.xin_off < 0) continue;
+        rom_handle* h = P.handles[t.prob];
+        const int nx = h->grid.nx, ny = h->grid.ny;
+        const bool xpos = (t.quad == 0 || t.quad == 3), ypos = (t.quad < 2);
+        const int fx = xpos ? ROM_FACE_LEFT : ROM_FACE_RIGHT;
+        const int fy = ypos ? ROM_FACE_BOTTOM : ROM_FACE_TOP;
+        const bool angok = in[t.sys].use_angular;
+        for (int k = 0; k < NO; ++k) {
+            const LaneDev& ld = P.lanes[t.ord_off + k];
+            const int u = P.user_of[t.sys][ld.ord];
+            if (u < 0) continue;
+            for (int jj = 0; jj < ny; ++jj) {
+                const int j = ypos ? jj : ny - 1 - jj;
+                double v = 0.0;
+                if (angok && !h->ang[fx].empty()) v = h->ang[fx][(size_t)u * ny + j];
+                else if (!h->face[fx].empty()) v = h->face[fx][j];
+                inf[t.xin_off + (int64_t)jj * NO + k] = v;
+            }
+            for (int ii = 0; ii < nx; ++ii) {
+                const int i = xpos ? ii : nx - 1 - ii;
+                double v = 0.0;
+                if (angok && !h->ang[fy].empty()) v = h->ang[fy][(size_t)u * nx + i];
+                else if (!h->face[fy].empty()) v = h->face[fy][i];
+                inf[t.yin_off + (int64_t)ii * NO + k] = v;
+            }
+        }
+    }
+    return inf;
+}
+
 // Boundary inflow of every wave-stream lane in sweep order, scaled by the lane's weight.
 std::vector<double> inflow_table(const Plan& P, const std::vector<SysInput>& in)
 {
@@ -386,6 +472,14 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     P.aniso = aniso;
     P.esz = P.fp64 ? 8 : 4;
     P.max_iter = max_iter;
+    P.kind = o.sweep == ROM_SWEEP_DIAG ? ROM_SWEEP_DIAG : ROM_SWEEP_STRIP;
+    if (P.kind == ROM_SWEEP_DIAG) {
+        if (aniso || psi_out || P.dd)
+            throw Fail{ROM_E_UNSUPPORTED, "the row-lane sweep takes isotropic sources, the step scheme and no angular-flux output"};
+        P.dR = o.diag_rows > 0 ? o.diag_rows : 16;
+        P.dK = o.diag_k > 0 ? o.diag_k : 1;
+        if (!diag_supported(P.fp64, P.dR, P.dK)) throw Fail{ROM_E_ARG, "unsupported row-lane sweep shape"};
+    }
     choose_tiles(o, in, P.fp64, P.tx, P.ty);
     if (!(P.fp64 ? sweep_tile_supported_fp64(P.tx, P.ty) : sweep_tile_supported(P.tx, P.ty)))
         throw Fail{ROM_E_ARG, P.fp64 ? "FP64 sweeps support tiles 8x4 and 8x8" : "unsupported tile shape"};
@@ -417,7 +511,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     // row-uniformity masks: bit r of (quadrant, strip, chunk) is set when sigma_t takes a single
     // value on the chunk's row r, so the sweep can take one reciprocal for the whole row
     std::vector<int32_t> uflags;
-    for (int p = 0; p < nprob; ++p) {
+    for (int p = 0; p < nprob && P.kind == ROM_SWEEP_STRIP; ++p) {
         rom_handle* h = P.handles[p];
         ProblemDev& pd = P.probs[p];
         pd.uflag_off = (int64_t)uflags.size();
@@ -466,7 +560,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     }
     P.L = Lb;
     std::vector<int> Lp(nprob, Lb);
-    {
+    if (P.kind == ROM_SWEEP_STRIP) {
         // strips per workgroup: a band long enough that most hand-offs stay in LDS
         int maxstrips = 1;
         for (auto& si : in) maxstrips = std::max(maxstrips, (si.h->grid.ny + TY - 1) / TY);
@@ -518,11 +612,66 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         P.sys_w[s] = in[s].w;
     }
 
-    // wave-streams, slots
+    // wave-streams (strip sweep) or tasks (row-lane sweep), slots
     int64_t part_sum = 0, edge_sum = 0, inflow_sum = 0;
     int prog_sum = 0;
     std::vector<std::vector<int>> sys_slots(P.nsys);
-    for (int p = 0; p < nprob; ++p) {
+    if (P.kind == ROM_SWEEP_DIAG) {
+        const int R = P.dR, K = P.dK, NO = (kWave / R) * K;
+        int maxblocks = 1;
+        for (auto& pd : P.probs) maxblocks = std::max(maxblocks, (pd.ny + R - 1) / R);
+        const int nbmax = diag_max_nb(P.fp64, K);
+        P.dNB = o.band > 0 ? std::min(o.band, nbmax) : std::min(maxblocks, nbmax);
+        P.wrap_cols = 0;
+        for (auto& pd : P.probs)
+            if ((pd.ny + R - 1) / R > P.dNB) P.wrap_cols = std::max(P.wrap_cols, pd.nx);
+        if (diag_lds_bytes(P.fp64, R, K, P.dNB, P.wrap_cols) > 160 * 1024)
+            throw Fail{ROM_E_UNSUPPORTED, "row-lane sweep: rows too long for the LDS row buffer"};
+        for (int sy = 0; sy < P.nsys; ++sy) {
+            const int p = P.sys[sy].prob;
+            rom_handle* h = P.handles[p];
+            const bool inflow = has_inflow(h, in);
+            std::vector<int>& uo = P.user_of[sy];
+            uo.clear();
+            for (int q = 0; q < 4; ++q) {
+                const auto& list = ql[sy].idx[q];
+                for (size_t b0 = 0; b0 < list.size(); b0 += NO) {
+                    DiagTaskDev t{};
+                    t.sys = sy;
+                    t.prob = p;
+                    t.quad = q;
+                    t.slot = P.nslots;
+                    t.ord_off = (int64_t)P.lanes.size();
+                    t.xin_off = t.yin_off = -1;
+                    if (inflow) {
+                        t.xin_off = inflow_sum;
+                        inflow_sum += (int64_t)h->grid.ny * NO;
+                        t.yin_off = inflow_sum;
+                        inflow_sum += (int64_t)h->grid.nx * NO;
+                    }
+                    for (int k = 0; k < NO; ++k) {
+                        LaneDev ld{};
+                        ld.ord = (int)uo.size();
+                        const int u = b0 + k < list.size() ? list[b0 + k] : -1;
+                        uo.push_back(u);
+                        if (u >= 0) {
+                            ld.a = std::fabs(in[sy].dirs[3 * u]) / h->dx;
+                            ld.b = std::fabs(in[sy].dirs[3 * u + 1]) / h->dy;
+                            ld.w = in[sy].w[u];
+                        }
+                        P.lanes.push_back(ld);
+                    }
+                    P.slot_off.push_back(part_sum);
+                    part_sum += h->cells;
+                    sys_slots[sy].push_back(P.nslots);
+                    ++P.nslots;
+                    P.dtasks.push_back(t);
+                }
+            }
+            P.npad_al[sy] = P.sys[sy].npad = (int)uo.size();
+        }
+    }
+    for (int p = 0; p < nprob && P.kind == ROM_SWEEP_STRIP; ++p) {
         rom_handle* h = P.handles[p];
         const int L = Lp[p], G = 64 / L;
         const ProblemDev& pd = P.probs[p];
@@ -606,6 +755,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
             if (bd < (P.probs[P.ws[k].prob].nstrips + P.band - 1) / P.band) P.tickets.push_back(make_int2(k, bd));
     P.ntickets = (int)P.tickets.size();
     P.grid = std::max(1, std::min(P.ntickets, device_cus() * 4));
+    if (P.kind == ROM_SWEEP_DIAG) P.grid = (int)P.dtasks.size();
     // combine blocks: about 512 blocks per launch (each thread keeps 4 cells in flight)
     {
         int64_t tot = 0;
@@ -626,6 +776,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     upload(P.d_slot_order, P.slot_order);
     upload(P.d_cblocks, P.cblocks);
     upload(P.d_uflags, uflags);
+    upload(P.d_dtasks, P.dtasks);
 
     auto cast_upload = [&](DevMem& d, const std::vector<double>& v) {
         if (P.fp64) {
@@ -642,20 +793,25 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         std::copy(h->ss.begin(), h->ss.end(), ss.begin() + field_off[p]);
         std::copy(h->q.begin(), h->q.end(), qv.begin() + field_off[p]);
     }
-    cast_upload(P.d_st, st);
+    {
+        std::vector<double> padded(fsum + 2 * kPoolPad, 1.0);  // padding: a harmless positive sigma_t
+        std::copy(st.begin(), st.end(), padded.begin() + kPoolPad);
+        cast_upload(P.d_st, padded);
+    }
     cast_upload(P.d_ss, ss);
     cast_upload(P.d_q, qv);
 
     // inflow in sweep order, scaled by the lane weight
     P.inflow_len = inflow_sum;
     if (inflow_sum > 0) {
-        const std::vector<double> inf = inflow_table(P, in);
+        const std::vector<double> inf = P.kind == ROM_SWEEP_DIAG ? diag_inflow_table(P, in) : inflow_table(P, in);
         cast_upload(P.d_inflow, inf);
     } else {
         HIPCHK(P.d_inflow.alloc(256));
     }
 
-    HIPCHK(P.d_src.alloc(phi_sum * P.esz));
+    HIPCHK(P.d_src.alloc((phi_sum + 2 * kPoolPad) * P.esz));
+    HIPCHK(hipMemset(P.d_src.p, 0, (phi_sum + 2 * kPoolPad) * P.esz));
     HIPCHK(P.d_phi.alloc(phi_sum * P.esz));
     HIPCHK(P.d_part.alloc(std::max<int64_t>(part_sum, 1) * P.esz));
     HIPCHK(P.d_edge.alloc(std::max<int64_t>(edge_sum, 1) * P.esz));
@@ -740,6 +896,49 @@ bool refresh_ordinates(Plan& P, const std::vector<SysInput>& in, hipStream_t s)
         const bool had = P.inflow_len > 0;
         if (!vacuum != had) return false;
     }
+    if (P.kind == ROM_SWEEP_DIAG) {
+        // same tasks in the same order: refill each task's ordinate entries
+        const int NO = (kWave / P.dR) * P.dK;
+        size_t ti = 0;
+        for (int k = 0; k < P.nsys; ++k) {
+            rom_handle* h = P.handles[P.sys[k].prob];
+            std::vector<int>& uo = P.user_of[k];
+            const size_t before = uo.size();
+            uo.clear();
+            for (int q = 0; q < 4; ++q) {
+                const auto& list = ql[k][q];
+                for (size_t b0 = 0; b0 < list.size(); b0 += NO) {
+                    if (ti >= P.dtasks.size()) throw Fail{ROM_E_STATE, "row-lane task layout changed"};
+                    const DiagTaskDev& t = P.dtasks[ti++];
+                    for (int o = 0; o < NO; ++o) {
+                        LaneDev& ld = P.lanes[t.ord_off + o];
+                        const int u = b0 + o < list.size() ? list[b0 + o] : -1;
+                        ld.ord = (int)uo.size();
+                        uo.push_back(u);
+                        ld.a = ld.b = ld.w = 0.0;
+                        if (u < 0) continue;
+                        ld.a = std::fabs(in[k].dirs[3 * u]) / h->dx;
+                        ld.b = std::fabs(in[k].dirs[3 * u + 1]) / h->dy;
+                        ld.w = in[k].w[u];
+                    }
+                }
+            }
+            if (uo.size() != before) throw Fail{ROM_E_STATE, "ordinate layout changed"};
+            P.sys_n[k] = in[k].n;
+            P.sys_w[k] = in[k].w;
+        }
+        rewrite(P.d_lanes, P.lanes, s);
+        if (P.inflow_len > 0) {
+            P.h_inflow = diag_inflow_table(P, in);
+            if (P.fp64) {
+                rewrite(P.d_inflow, P.h_inflow, s);
+            } else {
+                P.h_inflow32.assign(P.h_inflow.begin(), P.h_inflow.end());
+                rewrite(P.d_inflow, P.h_inflow32, s);
+            }
+        }
+        return true;
+    }
     // internal order: quadrant-major, L-lane groups, padded (as built)
     for (int k = 0; k < P.nsys; ++k) {
         std::vector<int>& uo = P.user_of[k];
@@ -801,8 +1000,7 @@ void enqueue_iteration(Plan& P, hipStream_t s, double tol)
             HIPCHK(launch_contract(c, P.fp64 ? 2 : 0, s));
         }
     }
-    const SweepArgs sa = P.sweep_args(0, 0);
-    HIPCHK(launch_sweep(sa, P.grid, P.fp64, P.tx, P.ty, P.dd, P.aniso, P.aniso ? (P.fp64 ? 1 : 2) : 0, P.L, s));
+    HIPCHK(P.launch_sweep_any(0, s));
     const CombineArgs ca = P.combine_args(0, tol);
     HIPCHK(launch_combine(ca, (int)P.cblocks.size(), P.fp64, s));
 }
@@ -813,7 +1011,7 @@ struct SolveResult {
     double ms = 0;
     double sweep_ms = 0;
     int sweeps = 0;
-    int tx = 0, ty = 0, band = 0, lanes = 0;
+    int tx = 0, ty = 0, band = 0, lanes = 0, kind = 0;
 };
 
 // Source iteration for every system of the plan.  The first iterate starts from phi = 0 (so the
@@ -841,7 +1039,7 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     HIPCHK(launch_fill(P.d_phi.p, phi_total, P.fp64, 0.0, s));
     for (auto& sd : P.sys) {
         const int64_t cells = P.handles[sd.prob]->cells;
-        HIPCHK(hipMemcpyAsync((char*)P.d_src.p + sd.src_off * P.esz, (char*)P.d_q.p + P.probs[sd.prob].field_off * P.esz,
+        HIPCHK(hipMemcpyAsync(P.src_ptr() + sd.src_off * P.esz, (char*)P.d_q.p + P.probs[sd.prob].field_off * P.esz,
                               cells * P.esz, hipMemcpyDeviceToDevice, s));
     }
     if (P.aniso) {
@@ -901,10 +1099,18 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     int most = 0;
     for (const SysCtl& c : r.sc) most = std::max(most, c.iter);
     P.last_iters = most;
-    r.tx = P.tx;
-    r.ty = P.ty;
-    r.band = P.band;
-    r.lanes = P.L;
+    r.kind = P.kind;
+    if (P.kind == ROM_SWEEP_DIAG) {
+        r.tx = P.dK;
+        r.ty = P.dR;
+        r.band = P.dNB;
+        r.lanes = P.dR;
+    } else {
+        r.tx = P.tx;
+        r.ty = P.ty;
+        r.band = P.band;
+        r.lanes = P.L;
+    }
     return r;
 }
 
@@ -933,7 +1139,15 @@ int validate_opts(rom_handle* h, const rom_si_opts* o, rom_si_opts& out)
     if (out.scheme != ROM_SCHEME_STEP && out.scheme != ROM_SCHEME_DD) return fail(h, ROM_E_ARG, "bad scheme");
     if (out.iters_per_check < 0) return fail(h, ROM_E_ARG, "iters_per_check must be >= 0");
     if (out.contract_split != 0) return fail(h, ROM_E_UNSUPPORTED, "split contraction is not built");
-    if (out.band < 0 || out.band > kMaxBand) return fail(h, ROM_E_ARG, "band must be 0..8");
+    if (out.sweep < ROM_SWEEP_AUTO || out.sweep > ROM_SWEEP_DIAG) return fail(h, ROM_E_ARG, "bad sweep kind");
+    if (out.band < 0 || out.band > (out.sweep == ROM_SWEEP_DIAG ? kDiagMaxWaves : kMaxBand))
+        return fail(h, ROM_E_ARG, "band must be 0..8 (strip sweep) or 0..16 (row-lane sweep)");
+    if (out.diag_rows != 0 && out.diag_rows != 16 && out.diag_rows != 64)
+        return fail(h, ROM_E_ARG, "diag_rows must be 0, 16 or 64");
+    if (out.diag_k != 0 && !diag_supported(out.precision == ROM_PREC_FP64, 16, out.diag_k))
+        return fail(h, ROM_E_ARG, "diag_k must be 0, 1, 2 or 4 (FP64: 0, 1, 2)");
+    if (out.sweep == ROM_SWEEP_DIAG && out.scheme != ROM_SCHEME_STEP)
+        return fail(h, ROM_E_UNSUPPORTED, "the row-lane sweep implements the step scheme only");
     if ((out.tile_x != 0 || out.tile_y != 0) && !sweep_tile_supported(out.tile_x, out.tile_y))
         return fail(h, ROM_E_ARG, "unsupported tile shape (8x4, 8x8, 16x8, 16x16, 32x16)");
     return ROM_OK;
@@ -942,8 +1156,8 @@ int validate_opts(rom_handle* h, const rom_si_opts* o, rom_si_opts& out)
 std::string plan_signature(const rom_si_opts& o, bool aniso, int kind, int nsys)
 {
     char buf[256];
-    std::snprintf(buf, sizeof buf, "k%d p%d s%d t%dx%d b%d a%d n%d mi%d", kind, o.precision, o.scheme, o.tile_x, o.tile_y,
-                  o.band, (int)aniso, nsys, o.max_iter);
+    std::snprintf(buf, sizeof buf, "k%d p%d s%d t%dx%d b%d a%d n%d mi%d w%d r%d q%d", kind, o.precision, o.scheme, o.tile_x,
+                  o.tile_y, o.band, (int)aniso, nsys, o.max_iter, o.sweep, o.diag_rows, o.diag_k);
     return buf;
 }
 
@@ -1140,6 +1354,7 @@ int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double
             if (!isfin(src[k])) return fail(h, ROM_E_DOMAIN, "non-finite source");
         std::vector<SysInput> in{{h, h->dirs.data(), h->w.data(), h->n, true}};
         std::unique_ptr<Plan> P(new Plan());
+        if (o.sweep == ROM_SWEEP_AUTO) o.sweep = ROM_SWEEP_STRIP;
         build_plan(*P, in, o, per, 0, psi != nullptr);
         hipStream_t s = h->stream();
         const SystemDev& sd = P->sys[0];
@@ -1158,10 +1373,10 @@ int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double
                 upload(P->d_ang, f);
             }
         } else {
-            if (P->fp64) HIPCHK(hipMemcpy(P->d_src.p, src, h->cells * 8, hipMemcpyHostToDevice));
+            if (P->fp64) HIPCHK(hipMemcpy(P->src_ptr(), src, h->cells * 8, hipMemcpyHostToDevice));
             else {
                 std::vector<float> f(src, src + h->cells);
-                HIPCHK(hipMemcpy(P->d_src.p, f.data(), h->cells * 4, hipMemcpyHostToDevice));
+                HIPCHK(hipMemcpy(P->src_ptr(), f.data(), h->cells * 4, hipMemcpyHostToDevice));
             }
         }
         const int psi_mode = psi ? 1 : 0;
@@ -1170,9 +1385,13 @@ int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double
             HIPCHK(P->d_psi.alloc(tot * P->esz));
         }
         HIPCHK(launch_reset_systems(P->d_sysctl.as<SysCtl>(), 1, P->d_ctl.as<Ctl>(), s));
-        SweepArgs sa = P->sweep_args(1, psi_mode);
-        // the sweep writes psi' into the angular layout when asked for it
-        HIPCHK(launch_sweep(sa, P->grid, P->fp64, P->tx, P->ty, P->dd, per, psi_mode, P->L, s));
+        if (P->kind == ROM_SWEEP_DIAG) {
+            HIPCHK(P->launch_sweep_any(1, s));
+        } else {
+            SweepArgs sa = P->sweep_args(1, psi_mode);
+            // the sweep writes psi' into the angular layout when asked for it
+            HIPCHK(launch_sweep(sa, P->grid, P->fp64, P->tx, P->ty, P->dd, per, psi_mode, P->L, s));
+        }
         const CombineArgs ca = P->combine_args(1, 0.0);
         HIPCHK(launch_combine(ca, (int)P->cblocks.size(), P->fp64, s));
         Ctl ctl{};
@@ -1216,12 +1435,13 @@ bool is_aniso(const rom_handle* h) { return h->scat != ROM_SCAT_ISO; }
 // Source iteration for a list of systems; fills stats and phis.
 // ------------------------------------------------------------------------------------ autotuner
 //
-// Tile shape (chunk x strip) and band (strips per workgroup) decide the sweep's pipeline depth,
-// per-chunk overhead and occupancy, and the best choice depends on the batch: a single small
-// problem wants short pipelines, a large ensemble wants occupancy.  The first solve of a batch
-// shape times each candidate on the real buffers (one warm-up and two timed sweeps each) and
-// caches the fastest for the process.  Results do not depend on the choice: the cell updates and
-// the lane-reduction tree are the same for every tile and band.
+// The sweep kernel (strip or row-lane) and its shape decide pipeline depth, per-step overhead
+// and occupancy, and the best choice depends on the batch: a single problem with few ordinates
+// wants the row-lane kernel's spatial parallelism, a large ensemble the strip kernel's in-lane
+// ordinate sums.  The first solve of a batch shape times each candidate on the real buffers (one
+// warm-up and two timed sweeps each) and caches the fastest for the process.  Every choice is
+// deterministic; strip tiles and bands give bitwise identical results, while the row-lane kernel
+// sums the ordinates of a cell in another (fixed) order.
 std::string tune_key(const std::vector<SysInput>& in, const rom_si_opts& o, bool aniso)
 {
     int maxnx = 0, maxny = 0, maxn = 0;
@@ -1233,8 +1453,8 @@ std::string tune_key(const std::vector<SysInput>& in, const rom_si_opts& o, bool
         work += s.h->cells * (int64_t)s.n;
     }
     char buf[160];
-    std::snprintf(buf, sizeof buf, "p%d s%d a%d k%zu x%d y%d n%d w%lld", o.precision, o.scheme, (int)aniso, in.size(),
-                  maxnx, maxny, maxn, (long long)work);
+    std::snprintf(buf, sizeof buf, "p%d s%d a%d k%zu x%d y%d n%d w%lld v%d r%d q%d", o.precision, o.scheme, (int)aniso,
+                  in.size(), maxnx, maxny, maxn, (long long)work, o.sweep, o.diag_rows, o.diag_k);
     return buf;
 }
 
@@ -1244,69 +1464,106 @@ bool autotune_enabled()
     return !(e && e[0] == '0');
 }
 
+// One candidate sweep configuration: strip (tile, band) or row-lane (rows, ordinates per lane).
+struct TuneChoice {
+    int sweep = 0, tx = 0, ty = 0, band = 0, rows = 0, k = 0;
+};
+
+void apply_choice(const TuneChoice& c, rom_si_opts& o)
+{
+    o.sweep = c.sweep;
+    if (c.sweep == ROM_SWEEP_STRIP) {
+        o.tile_x = c.tx;
+        o.tile_y = c.ty;
+        o.band = c.band;
+    } else {
+        o.diag_rows = c.rows;
+        o.diag_k = c.k;
+    }
+}
+
+// Time three sweeps of every candidate on the real buffers of this batch shape (zero sources) and
+// keep the fastest for the process.  Candidates: the strip kernel's tiles x bands, and, for
+// isotropic step-scheme problems, the row-lane kernel's (rows, ordinates per lane).
 void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t s)
 {
-    static std::map<std::string, std::pair<std::pair<int, int>, int>> cache;
+    static std::map<std::string, TuneChoice> cache;
     const std::string key = tune_key(in, o, aniso);
     auto it = cache.find(key);
     if (it != cache.end()) {
-        o.tile_x = it->second.first.first;
-        o.tile_y = it->second.first.second;
-        o.band = it->second.second;
+        apply_choice(it->second, o);
         return;
     }
     const bool fp64 = o.precision == ROM_PREC_FP64;
-    std::vector<std::pair<int, int>> tiles = fp64 ? std::vector<std::pair<int, int>>{{8, 4}, {8, 8}}
-                                                  : std::vector<std::pair<int, int>>{{8, 4}, {8, 8}, {16, 8}, {16, 16}};
+    std::vector<TuneChoice> cands;
+    if (o.sweep != ROM_SWEEP_DIAG) {
+        const std::vector<std::pair<int, int>> tiles = fp64 ? std::vector<std::pair<int, int>>{{8, 4}, {8, 8}}
+                                                            : std::vector<std::pair<int, int>>{{8, 4}, {8, 8}, {16, 8}, {16, 16}};
+        for (auto t : tiles)
+            for (int band : {2, 4, 8}) cands.push_back({ROM_SWEEP_STRIP, t.first, t.second, band, 0, 0});
+    }
+    if (o.sweep != ROM_SWEEP_STRIP && !aniso && o.scheme == ROM_SCHEME_STEP) {
+        for (int rows : {16, 64})
+            for (int k : {1, 2, 4})
+                if (diag_supported(fp64, rows, k) && (o.diag_rows == 0 || o.diag_rows == rows) && (o.diag_k == 0 || o.diag_k == k))
+                    cands.push_back({ROM_SWEEP_DIAG, 0, 0, 0, rows, k});
+    }
     float best = 1e30f;
-    int bx = 0, by = 0, bb = 0;
+    TuneChoice pick;
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
-    for (auto t : tiles) {
-        for (int band : {2, 4, 8}) {
-            rom_si_opts c = o;
-            c.tile_x = t.first;
-            c.tile_y = t.second;
-            c.band = band;
-            Plan P;
-            try {
-                build_plan(P, in, c, aniso, 1);
-            } catch (const Fail&) {
-                continue;  // band does not fit this tile's LDS
-            }
-            if (P.band != band || sweep_lds_bytes(P.fp64, P.tx, P.ty, aniso, P.L, P.band) > 64 * 1024) continue;
-            int64_t tot = 0;
-            for (auto& sd : P.sys) tot = std::max<int64_t>(tot, sd.phi_off + P.handles[sd.prob]->cells);
-            HIPCHK(launch_fill(P.d_src.p, tot, P.fp64, 0.0, s));
-            if (aniso) HIPCHK(launch_fill(P.d_ang.p, (int64_t)(P.d_ang.bytes / P.esz), P.fp64, 0.0, s));
-            const SweepArgs sa = P.sweep_args(1, 0);
-            float ms = 0.f;
-            for (int rep = 0; rep < 3; ++rep) {
-                HIPCHK(launch_reset_systems(P.d_sysctl.as<SysCtl>(), P.nsys, P.d_ctl.as<Ctl>(), s));
-                if (rep == 1) HIPCHK(hipEventRecord(e0, s));
-                HIPCHK(launch_sweep(sa, P.grid, P.fp64, P.tx, P.ty, P.dd, aniso, aniso ? (P.fp64 ? 1 : 2) : 0, P.L, s));
-            }
-            HIPCHK(hipEventRecord(e1, s));
-            HIPCHK(hipEventSynchronize(e1));
-            HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-            Ctl ctl{};
-            HIPCHK(hipMemcpy(&ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost));
-            if (!ctl.error && ms < best) {
-                best = ms;
-                bx = P.tx;
-                by = P.ty;
-                bb = P.band;
+    for (const TuneChoice& cand : cands) {
+        rom_si_opts c = o;
+        apply_choice(cand, c);
+        Plan P;
+        try {
+            build_plan(P, in, c, aniso, 1);
+        } catch (const Fail&) {
+            continue;  // does not fit (LDS) or not supported for this batch
+        }
+        if (cand.sweep == ROM_SWEEP_STRIP &&
+            (P.band != cand.band || sweep_lds_bytes(P.fp64, P.tx, P.ty, aniso, P.L, P.band) > 64 * 1024))
+            continue;
+        int64_t tot = 0;
+        for (auto& sd : P.sys) tot = std::max<int64_t>(tot, sd.phi_off + P.handles[sd.prob]->cells);
+        HIPCHK(launch_fill(P.src_ptr(), tot, P.fp64, 0.0, s));
+        if (aniso) HIPCHK(launch_fill(P.d_ang.p, (int64_t)(P.d_ang.bytes / P.esz), P.fp64, 0.0, s));
+        float ms = 0.f;
+        for (int rep = 0; rep < 3; ++rep) {
+            HIPCHK(launch_reset_systems(P.d_sysctl.as<SysCtl>(), P.nsys, P.d_ctl.as<Ctl>(), s));
+            if (rep == 1) HIPCHK(hipEventRecord(e0, s));
+            HIPCHK(P.launch_sweep_any(1, s));
+        }
+        HIPCHK(hipEventRecord(e1, s));
+        HIPCHK(hipEventSynchronize(e1));
+        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        Ctl ctl{};
+        HIPCHK(hipMemcpy(&ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost));
+        // the row-lane kernel writes one partial slot per task: charge the combine step's extra
+        // reads (about 4 bytes per cell per slot at ~4 TB/s) so fewer, fuller slots can win
+        double extra = 0.0;
+        if (cand.sweep == ROM_SWEEP_DIAG) {
+            int64_t bytes = 0;
+            for (auto& sd : P.sys) bytes += (int64_t)sd.nslots * P.handles[sd.prob]->cells * P.esz;
+            extra = (double)bytes / 4.0e9;  // ms
+        }
+        const float score = ms + (float)extra;
+        if (!ctl.error && score < best) {
+            best = score;
+            pick = cand;
+            if (cand.sweep == ROM_SWEEP_STRIP) {
+                pick.tx = P.tx;
+                pick.ty = P.ty;
+                pick.band = P.band;
             }
         }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    if (bx == 0) return;  // nothing measurable: keep the heuristic
-    cache[key] = {{bx, by}, bb};
-    o.tile_x = bx;
-    o.tile_y = by;
-    o.band = bb;
+    if (pick.sweep == 0) return;  // nothing measurable: keep the heuristic
+    cache[key] = pick;
+    apply_choice(pick, o);
 }
 
 // reuse: 0 build a new plan, 1 run the cached plan as it is, 2 refresh its ordinate tables first
@@ -1320,7 +1577,9 @@ int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opt
     rom_si_opts o = o_in;
     if (reuse == 2 && slot && !refresh_ordinates(*slot, in, owner->stream())) reuse = 0;
     if (reuse == 0 || !slot) {
-        if (o.tile_x == 0 && o.band == 0 && autotune_enabled()) autotune(in, o, aniso, owner->stream());
+        const bool free_shape = o.sweep == ROM_SWEEP_DIAG ? (o.diag_rows == 0 || o.diag_k == 0)
+                                                          : (o.tile_x == 0 && o.band == 0);
+        if (free_shape && autotune_enabled()) autotune(in, o, aniso, owner->stream());
         slot.reset(new Plan());
         build_plan(*slot, in, o, aniso, o.max_iter);
         if (aniso) build_kernel_matrices(*slot, in);
@@ -1368,6 +1627,7 @@ int rom_source_iterate(rom_handle* h, const rom_si_opts* opts, double* phi, rom_
             stats->tile_y = res.ty;
             stats->band = res.band;
             stats->lanes = res.lanes;
+            stats->sweep = res.kind;
         }
         if (sc.state == 3) return fail(h, ROM_E_DIVERGED, "non-finite iterate");
         return sc.state == 1 ? ROM_OK : ROM_NOT_CONVERGED;
@@ -1431,6 +1691,7 @@ int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, d
                 stats[i].tile_y = res.ty;
                 stats[i].band = res.band;
                 stats[i].lanes = res.lanes;
+                stats[i].sweep = res.kind;
             }
             if (sc.state == 3) worst = ROM_E_DIVERGED;
             else if (sc.state != 1 && worst == ROM_OK) worst = ROM_NOT_CONVERGED;
@@ -1475,7 +1736,7 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
         int done = 0, min_it = 1 << 30, max_it = 0, worst = ROM_OK, sweeps = 0;
         int64_t updates = 0;
         double ms = 0, sweep_ms = 0;
-        int shape[4] = {0, 0, 0, 0};
+        int shape[5] = {0, 0, 0, 0, 0};
         // one plan per batch shape, refreshed with each batch's ordinates
         std::unique_ptr<Plan>& P = h->ens_plan;
         std::vector<int64_t> offs;
@@ -1502,6 +1763,7 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
             shape[1] = res.ty;
             shape[2] = res.band;
             shape[3] = res.lanes;
+            shape[4] = res.kind;
             offs.assign(b, 0);
             for (int k = 0; k < b; ++k) {
                 offs[k] = P->sys[k].phi_off;
@@ -1543,6 +1805,7 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
             stats->tile_y = shape[1];
             stats->band = shape[2];
             stats->lanes = shape[3];
+            stats->sweep = shape[4];
         }
         if (worst == ROM_E_DIVERGED) return fail(h, ROM_E_DIVERGED, "non-finite iterate in a sample");
         return worst;

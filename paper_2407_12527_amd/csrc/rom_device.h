@@ -62,6 +62,21 @@ struct SystemDev {
     int64_t ang_off;            // anisotropic source / angular flux [cells][npad] (elements)
 };
 
+// Task of the row-lane ("diagonal") sweep: one workgroup sweeps the whole grid of one problem for
+// NO = (64 / R) * K ordinates of one quadrant of one system.  Lane g*R + r holds row r of an
+// R-row block for ordinates g*K .. g*K + K - 1 (the group's entries ord_off + g*K + k of the lane
+// table).  Its wavefronts take the row blocks in turn (block b -> wave b mod NB).
+constexpr int kDiagMaxWaves = 16;
+constexpr int kPoolPad = 128;   // elements of padding before and after the sigma_t and source pools
+
+struct DiagTaskDev {
+    int32_t sys, prob, quad;
+    int32_t slot;               // partial-flux slot
+    int64_t ord_off;            // first of the task's NO lane-table entries
+    int64_t xin_off;            // inflow on the entry x-face [ny][NO], rows in sweep order; -1 vacuum
+    int64_t yin_off;            // inflow on the entry y-face [nx][NO], columns in sweep order; -1 vacuum
+};
+
 // Per-system convergence state, written only by the combine step.
 struct SysCtl {
     unsigned long long dmax_bits;   // max |phi^k - phi^{k-1}| of the running iteration (FP64 bits)

@@ -32,6 +32,25 @@ struct SweepArgs {
     SysCtl* sysctl;
 };
 
+struct DiagArgs {
+    const DiagTaskDev* tasks;
+    const LaneDev* ords;       // [tasks][NO] (a, b, w of each ordinate; padding has w = 0)
+    const ProblemDev* probs;
+    const SystemDev* sys;
+    int32_t spin_limit;
+    int32_t mode_all;
+    int32_t wrap_cols;         // columns of the LDS row buffer that carries a block's top row to
+                               // the next round of the workgroup's waves (0: one round suffices)
+    int32_t pad;
+    const void* sigma_t;       // field pool (T)
+    const void* src;           // isotropic source pool (T)
+    void* part;                // partial scalar-flux pool (T)
+    const int64_t* slot_off;
+    const void* inflow;        // unweighted boundary inflow pool (T)
+    Ctl* ctl;
+    SysCtl* sysctl;
+};
+
 struct CombineArgs {
     const SystemDev* sys;
     const ProblemDev* probs;
@@ -81,6 +100,12 @@ hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty,
 bool sweep_tile_supported(int tx, int ty);
 bool sweep_tile_supported_fp64(int tx, int ty);
 size_t sweep_lds_bytes(bool fp64, int tx, int ty, bool ang, int L, int nw);
+// Row-lane sweep: R rows per lane block (16 or 64), K ordinates per lane (1, 2, 4; FP64: 1, 2),
+// nb wavefronts per workgroup (1..16), one workgroup per task.
+bool diag_supported(bool fp64, int R, int K);
+int diag_max_nb(bool fp64, int K);
+size_t diag_lds_bytes(bool fp64, int R, int K, int nb, int wrap_cols);
+hipError_t launch_diag(const DiagArgs& a, int ntasks, int nb, bool fp64, int R, int K, hipStream_t s);
 hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s);
 hipError_t launch_sweep_prologue(Ctl* ctl, hipStream_t s);
 hipError_t launch_reset_systems(SysCtl* sc, int nsys, Ctl* ctl, hipStream_t s);

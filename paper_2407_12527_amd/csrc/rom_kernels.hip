@@ -408,6 +408,31 @@ hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty,
     return hipErrorInvalidValue;
 }
 
+hipError_t launch_diag_f32(const DiagArgs&, int, int, int, int, hipStream_t);
+hipError_t launch_diag_f64(const DiagArgs&, int, int, int, int, hipStream_t);
+
+int diag_max_nb(bool fp64, int K) { return K * (fp64 ? 8 : 4) >= 16 ? 8 : kDiagMaxWaves; }
+
+bool diag_supported(bool fp64, int R, int K)
+{
+    if (R != 16 && R != 64) return false;
+    return fp64 ? (K == 1 || K == 2) : (K == 1 || K == 2 || K == 4);
+}
+
+size_t diag_lds_bytes(bool fp64, int R, int K, int nb, int wrap_cols)
+{
+    const size_t no = (size_t)(kWave / R) * K;
+    const size_t ring = R == 16 ? 64 : 128;
+    return (fp64 ? 8 : 4) * (((size_t)(nb - 1) * ring + (size_t)wrap_cols) * no + (size_t)kWave * K) +
+           sizeof(int) * 2 * kDiagMaxWaves;
+}
+
+hipError_t launch_diag(const DiagArgs& a, int ntasks, int nb, bool fp64, int R, int K, hipStream_t s)
+{
+    if (!diag_supported(fp64, R, K)) return hipErrorInvalidValue;
+    return fp64 ? launch_diag_f64(a, ntasks, nb, R, K, s) : launch_diag_f32(a, ntasks, nb, R, K, s);
+}
+
 hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s)
 {
     if (fp64)

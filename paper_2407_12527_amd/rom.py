@@ -33,6 +33,7 @@ ROM_SCHEME_STEP, ROM_SCHEME_DD = 0, 1
 ROM_SCAT_ISO, ROM_SCAT_LINEAR, ROM_SCAT_HG, ROM_SCAT_DENSE = 0, 1, 2, 3
 ROM_ORD_STRATIFIED, ROM_ORD_IID_SPHERE, ROM_ORD_UNIFORM2D, ROM_ORD_GAUSS2D = 0, 1, 2, 3
 ROM_PREC_FP32, ROM_PREC_FP64 = 0, 1
+ROM_SWEEP_AUTO, ROM_SWEEP_STRIP, ROM_SWEEP_DIAG = 0, 1, 2
 ROM_FACE_LEFT, ROM_FACE_RIGHT, ROM_FACE_BOTTOM, ROM_FACE_TOP = 0, 1, 2, 3
 
 # every function declared in include/rom.h
@@ -58,20 +59,21 @@ class rom_ord_spec(C.Structure):
 class rom_si_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32), ("scheme", C.c_int32),
                 ("iters_per_check", C.c_int32), ("tile_x", C.c_int32), ("tile_y", C.c_int32),
-                ("contract_split", C.c_int32), ("band", C.c_int32), ("reserved", C.c_int32 * 3)]
+                ("contract_split", C.c_int32), ("band", C.c_int32), ("sweep", C.c_int32), ("diag_rows", C.c_int32),
+                ("diag_k", C.c_int32)]
 
 
 class rom_si_stats(C.Structure):
     _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("final_r", C.c_double), ("updates", C.c_int64),
                 ("device_ms", C.c_double), ("sweep_ms", C.c_double), ("sweeps", C.c_int32), ("tile_x", C.c_int32),
-                ("tile_y", C.c_int32), ("band", C.c_int32), ("lanes", C.c_int32), ("pad", C.c_int32)]
+                ("tile_y", C.c_int32), ("band", C.c_int32), ("lanes", C.c_int32), ("sweep", C.c_int32)]
 
 
 class rom_ens_stats(C.Structure):
     _fields_ = [("samples", C.c_int32), ("min_iters", C.c_int32), ("max_iters", C.c_int32), ("status", C.c_int32),
                 ("updates", C.c_int64), ("device_ms", C.c_double), ("sweep_ms", C.c_double), ("sweeps", C.c_int32),
                 ("tile_x", C.c_int32), ("tile_y", C.c_int32), ("band", C.c_int32), ("lanes", C.c_int32),
-                ("pad", C.c_int32)]
+                ("sweep", C.c_int32)]
 
 
 def library_path() -> str:
@@ -212,7 +214,7 @@ def _check(st, h=None):
 
 
 def si_opts(tol=1e-6, max_iter=1000, precision=ROM_PREC_FP32, scheme=ROM_SCHEME_STEP, iters_per_check=0,
-            tile=(0, 0), contract_split=0, band=0) -> rom_si_opts:
+            tile=(0, 0), contract_split=0, band=0, sweep=0, diag_rows=0, diag_k=0) -> rom_si_opts:
     o = rom_si_opts()
     o.tol = tol
     o.max_iter = max_iter
@@ -222,6 +224,9 @@ def si_opts(tol=1e-6, max_iter=1000, precision=ROM_PREC_FP32, scheme=ROM_SCHEME_
     o.tile_x, o.tile_y = tile
     o.contract_split = contract_split
     o.band = band
+    o.sweep = sweep
+    o.diag_rows = diag_rows
+    o.diag_k = diag_k
     return o
 
 

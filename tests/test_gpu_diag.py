@@ -1,0 +1,212 @@
+"""GPU parity of the row-lane ("diagonal") sweep kernel against the FP64 oracle.
+
+Covers the lane shapes (16- and 64-row blocks, 1, 2 or 4 ordinates per lane, FP32 and FP64),
+grids that are ragged against the 16/64-row blocks and the 8-step unroll, degenerate grids,
+inflow on every face, wavefront counts that force several rounds through the workgroup (the
+row buffer that carries a block's top row from the last wavefront to the first), quadrants with
+fewer ordinates than a task holds, source iteration, batches, ensembles and refreshed plans.
+Bars as in the other parity tests: FP32 1e-5 normwise for phi (2e-6 for single sweeps), FP64 1e-12
+(single sweeps) and 1e-11 (fixed iteration counts)."""
+import numpy as np
+import pytest
+
+import rom_inputs as RI
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_12527_amd import rom
+    rom.lib()
+    return rom
+
+
+def nrm(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def rand_problem(rng, nx, ny, ratio=0.9):
+    st = rng.uniform(0.5, 3.0, nx * ny)
+    ss = st * rng.uniform(0.0, ratio, nx * ny)
+    q = rng.uniform(0.0, 2.0, nx * ny)
+    return st, ss, q
+
+
+def diag_opts(R, prec, rows, k, band=0, **kw):
+    return R.si_opts(precision=R.ROM_PREC_FP64 if prec == "fp64" else R.ROM_PREC_FP32, sweep=R.ROM_SWEEP_DIAG,
+                     diag_rows=rows, diag_k=k, band=band, **kw)
+
+
+SHAPES = [(16, 1), (16, 2), (16, 4), (64, 1), (64, 2), (64, 4)]
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("rows,k", SHAPES)
+def test_single_sweep_shapes(R, orc, prec, rows, k):
+    if prec == "fp64" and k == 4:
+        pytest.skip("FP64 row-lane sweeps take 1 or 2 ordinates per lane")
+    rng = np.random.default_rng(101)
+    nx, ny = 37, 83
+    st, ss, q = rand_problem(rng, nx, ny)
+    inflow = {"left": rng.uniform(0, 1, ny), "right": rng.uniform(0, 1, ny), "bottom": rng.uniform(0, 1, nx),
+              "top": rng.uniform(0, 1, nx)}
+    h = R.Handle(nx, ny, st, ss, q, box=(0.0, 1.3, 0.0, 0.7), inflow=inflow)
+    p = orc.Problem(nx, ny, st, ss, q, box=(0.0, 1.3, 0.0, 0.7), inflow=inflow)
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 2, 3, seed=5, sample=1)
+    h.set_ordinates(d, w)
+    S = rng.uniform(0.0, 3.0, nx * ny)
+    phi = h.sweep(S, diag_opts(R, prec, rows, k))
+    ref = orc.scalar_flux(w, orc.sweep(p, d, S))
+    assert nrm(phi, ref) < (1e-12 if prec == "fp64" else 2e-6)
+
+
+@pytest.mark.parametrize("shape", [(1, 1), (1, 17), (23, 1), (5, 3), (8, 16), (9, 65), (130, 7)])
+@pytest.mark.parametrize("rows", [16, 64])
+def test_single_sweep_degenerate_and_ragged(R, orc, shape, rows):
+    rng = np.random.default_rng(102)
+    nx, ny = shape
+    st, ss, q = rand_problem(rng, nx, ny)
+    inflow = {"left": rng.uniform(0, 1, ny), "top": rng.uniform(0, 1, nx)}
+    h = R.Handle(nx, ny, st, ss, q, inflow=inflow)
+    p = orc.Problem(nx, ny, st, ss, q, inflow=inflow)
+    d, w = R.generate_ordinates(R.ROM_ORD_IID_SPHERE, 11, seed=7)
+    h.set_ordinates(d, w)
+    S = rng.uniform(0.0, 1.0, nx * ny)
+    phi = h.sweep(S, diag_opts(R, "fp64", rows, 1))
+    ref = orc.scalar_flux(w, orc.sweep(p, d, S))
+    assert nrm(phi, ref) < 1e-12
+
+
+@pytest.mark.parametrize("band", [1, 2, 3, 16])
+@pytest.mark.parametrize("rows", [16, 64])
+def test_single_sweep_rounds(R, orc, band, rows):
+    """More row blocks than wavefronts: blocks go round the workgroup several times (the last
+    wavefront hands its top row to the first through the LDS row buffer)."""
+    rng = np.random.default_rng(103)
+    nx, ny = 45, 300
+    st, ss, q = rand_problem(rng, nx, ny)
+    inflow = {"right": rng.uniform(0, 1, ny), "bottom": rng.uniform(0, 1, nx)}
+    h = R.Handle(nx, ny, st, ss, q, inflow=inflow)
+    p = orc.Problem(nx, ny, st, ss, q, inflow=inflow)
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 2, 2, seed=9)
+    h.set_ordinates(d, w)
+    S = rng.uniform(0.0, 1.0, nx * ny)
+    phi = h.sweep(S, diag_opts(R, "fp32", rows, 2, band=band))
+    ref = orc.scalar_flux(w, orc.sweep(p, d, S))
+    assert nrm(phi, ref) < 2e-6
+
+
+def test_single_sweep_angular_inflow(R, orc):
+    rng = np.random.default_rng(104)
+    nx, ny = 23, 41
+    st, ss, q = rand_problem(rng, nx, ny)
+    h = R.Handle(nx, ny, st, ss, q)
+    d, w = R.generate_ordinates(R.ROM_ORD_IID_SPHERE, 19, seed=3)
+    h.set_ordinates(d, w)
+    n = len(w)
+    ang = {"right": rng.uniform(0, 2, (n, ny)), "bottom": rng.uniform(0, 2, (n, nx))}
+    h.set_inflow_angular(R.ROM_FACE_RIGHT, ang["right"])
+    h.set_inflow_angular(R.ROM_FACE_BOTTOM, ang["bottom"])
+    p = orc.Problem(nx, ny, st, ss, q, inflow_angular={k: np.ascontiguousarray(v) for k, v in ang.items()})
+    S = rng.uniform(0.0, 1.0, nx * ny)
+    phi = h.sweep(S, diag_opts(R, "fp64", 16, 2))
+    assert nrm(phi, orc.scalar_flux(w, orc.sweep(p, d, S))) < 1e-12
+
+
+def test_refuses_unsupported(R):
+    h = R.Handle(8, 8, np.ones(64), np.full(64, 0.5), np.ones(64))
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 1, 2)
+    h.set_ordinates(d, w)
+    with pytest.raises(R.RomError) as ei:
+        h.sweep(np.ones(64), diag_opts(R, "fp32", 16, 1), want_psi=True)
+    assert ei.value.status == R.ROM_E_UNSUPPORTED
+    with pytest.raises(R.RomError) as ei:
+        h.source_iterate(diag_opts(R, "fp32", 16, 1, scheme=R.ROM_SCHEME_DD))
+    assert ei.value.status == R.ROM_E_UNSUPPORTED
+    with pytest.raises(R.RomError) as ei:
+        h.source_iterate(diag_opts(R, "fp64", 16, 4))
+    assert ei.value.status == R.ROM_E_ARG
+
+
+# ------------------------------------------------------------------------------------ source iteration
+@pytest.mark.parametrize("rows,k", [(16, 1), (16, 4), (64, 2)])
+def test_si_c2_full_size(R, orc, rows, k):
+    """Workload c2 (256 x 256 checkerboard, 256 stratified ordinates, FP32, tol 1e-6)."""
+    f = RI.c2().fields[0]
+    h = R.Handle(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    p = orc.Problem(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 8, 8, seed=0)
+    h.set_ordinates(d, w)
+    phi, st, rc = h.source_iterate(diag_opts(R, "fp32", rows, k, tol=1e-6))
+    ref = orc.source_iterate(p, d, w, None, tol=1e-6)
+    assert rc == 0 and abs(st.iters - ref["iters"]) <= 1 and st.sweep == R.ROM_SWEEP_DIAG
+    assert nrm(phi, ref["phi"]) < 1e-5
+    P = phi.reshape(256, 256)
+    assert nrm(P[:, ::-1], P) < 1e-6 and nrm(P[::-1, :], P) < 1e-6
+    phi2, _, _ = h.source_iterate(diag_opts(R, "fp32", rows, k, tol=1e-6))
+    assert np.array_equal(phi, phi2)
+
+
+def test_si_c1_fp64_fixed_iterations(R, orc):
+    wl = RI.c1()
+    f = wl.fields[0]
+    h = R.Handle(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    p = orc.Problem(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    d, w = R.generate_ordinates(R.ROM_ORD_IID_SPHERE, 32, seed=0)
+    h.set_ordinates(d, w)
+    phi, st, rc = h.source_iterate(diag_opts(R, "fp64", 16, 1, tol=-1.0, max_iter=6))
+    ref = orc.source_iterate(p, d, w, None, tol=0.0, max_iter=6)
+    assert st.iters == 6 and nrm(phi, ref["phi"]) < 1e-11
+    phi, st, rc = h.source_iterate(diag_opts(R, "fp64", 16, 1, tol=1e-8))
+    ref = orc.source_iterate(p, d, w, None, tol=1e-8)
+    assert rc == 0 and st.iters == ref["iters"] and nrm(phi, ref["phi"]) < 1e-9
+
+
+def test_batch_uneven_and_refresh(R, orc):
+    wl = RI.c5(count=6, sides=(16, 40, 100, 300), m_range=(4, 40), master_seed=5)
+    hs, probs, sets = [], [], []
+    for k, f in enumerate(wl.fields):
+        hs.append(R.Handle(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q))
+        probs.append(orc.Problem(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q))
+        nz, nt = orc.stratified_spec(wl.n_ord[k])
+        sets.append(R.generate_ordinates(R.ROM_ORD_STRATIFIED, nz, nt, seed=wl.problem_seed(k)))
+        hs[-1].set_ordinates(*sets[-1])
+    o = diag_opts(R, "fp32", 16, 2, tol=1e-6)
+    for rep in range(2):
+        outs, stats, rc = R.solve_batch(hs, o)
+        assert rc == 0
+        for k in range(len(hs)):
+            ref = orc.source_iterate(probs[k], sets[k][0], sets[k][1], None, tol=1e-6)["phi"]
+            assert nrm(outs[k], ref) < 1e-5, (rep, k)
+        nz, nt = orc.stratified_spec(wl.n_ord[1])
+        sets[1] = R.generate_ordinates(R.ROM_ORD_STRATIFIED, nz, nt, seed=wl.problem_seed(1), sample=3)
+        hs[1].set_ordinates(*sets[1])
+
+
+def test_ensemble(R, orc):
+    nx, ny = 96, 80
+    f = RI.uniform_fields(nx, ny, 1.0, 0.5, 0.45, 0.55)
+    h = R.Handle(nx, ny, f.sigma_t, f.sigma_s, f.q)
+    p = orc.Problem(nx, ny, f.sigma_t, f.sigma_s, f.q)
+    for seed in (7, 8):
+        mean, var, st, rc = h.ensemble(6, seed, R.ROM_ORD_STRATIFIED, 4, 8, diag_opts(R, "fp32", 64, 1, tol=1e-7))
+        ref = orc.ensemble(p, orc.ORD_STRATIFIED, 4, 8, seed, 6, tol=1e-7)
+        assert rc == 0 and st.sweep == R.ROM_SWEEP_DIAG
+        assert nrm(mean, ref["mean"]) < 1e-5 and nrm(var, ref["var"]) < 2e-3
+
+
+def test_autotune_picks_a_valid_kernel(R, orc):
+    """Automatic choice (strip or row-lane) on c2: the result meets the bar whichever wins."""
+    f = RI.c2().fields[0]
+    h = R.Handle(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    p = orc.Problem(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 8, 8, seed=0)
+    h.set_ordinates(d, w)
+    phi, st, rc = h.source_iterate(R.si_opts(tol=1e-6))
+    assert rc == 0 and st.sweep in (R.ROM_SWEEP_STRIP, R.ROM_SWEEP_DIAG)
+    ref = orc.source_iterate(p, d, w, None, tol=1e-6)
+    assert nrm(phi, ref["phi"]) < 1e-5

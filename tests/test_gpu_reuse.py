@@ -147,5 +147,9 @@ def test_autotuned_shape_reported(R):
     h.set_ordinates(d, w)
     _, st, rc = h.source_iterate(R.si_opts(tol=1e-6))
     assert rc == 0
-    assert (st.tile_x, st.tile_y) in ((8, 4), (8, 8), (16, 8), (16, 16))
-    assert 1 <= st.band <= 8 and st.lanes in (16, 32, 64)
+    if st.sweep == R.ROM_SWEEP_STRIP:
+        assert (st.tile_x, st.tile_y) in ((8, 4), (8, 8), (16, 8), (16, 16))
+        assert 1 <= st.band <= 8 and st.lanes in (16, 32, 64)
+    else:
+        assert st.sweep == R.ROM_SWEEP_DIAG
+        assert st.tile_y in (16, 64) and st.tile_x in (1, 2, 4) and 1 <= st.band <= 16
