@@ -49,10 +49,20 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--tile", default="0x0", help="sweep chunk x strip size, e.g. 8x4 (0x0: automatic)")
-    ap.add_argument("--band", type=int, default=0, help="strips per sweep workgroup (0: automatic)")
+    ap.add_argument("--band", type=int, default=0,
+                    help="strips (strip sweep) or row blocks (row-lane sweep) per workgroup (0: automatic)")
+    ap.add_argument("--sweep", default="auto", choices=["auto", "strip", "diag"],
+                    help="sweep kernel (auto: the autotuner's choice)")
+    ap.add_argument("--diag-rows", type=int, default=0, help="row-lane sweep: rows per lane block (16, 64)")
+    ap.add_argument("--diag-k", type=int, default=0, help="row-lane sweep: ordinates per lane (1, 2, 4)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run a device-to-device copy of BYTES (reference for HBM byte counters)")
     return ap.parse_args()
+
+
+def kernel_opts(a, R):
+    kind = {"auto": R.ROM_SWEEP_AUTO, "strip": R.ROM_SWEEP_STRIP, "diag": R.ROM_SWEEP_DIAG}[a.sweep]
+    return {"sweep": kind, "diag_rows": a.diag_rows, "diag_k": a.diag_k}
 
 
 def sweep_shape(shape):
@@ -117,7 +127,7 @@ def bench_batch(a, wl, R, torch):
         h.set_ordinates(d, w)
         hs.append(h)
     tile = tuple(int(v) for v in a.tile.lower().split("x"))
-    opts = R.si_opts(tol=wl.tol, max_iter=wl.max_iter, tile=tile, band=a.band)
+    opts = R.si_opts(tol=wl.tol, max_iter=wl.max_iter, tile=tile, band=a.band, **kernel_opts(a, R))
     for _ in range(a.warmup):
         R.solve_batch(hs, opts)
     torch.cuda.synchronize()
@@ -191,7 +201,7 @@ def main():
     fp64 = wl.precision == "fp64"
     prec = R.ROM_PREC_FP64 if fp64 else R.ROM_PREC_FP32
     tile = tuple(int(v) for v in a.tile.lower().split("x"))
-    opts = R.si_opts(tol=wl.tol, max_iter=wl.max_iter, precision=prec, tile=tile, band=a.band)
+    opts = R.si_opts(tol=wl.tol, max_iter=wl.max_iter, precision=prec, tile=tile, band=a.band, **kernel_opts(a, R))
     if wl.ord_kind == "stratified":
         m = n // 4
         nz = max(d for d in range(1, int(m ** 0.5) + 1) if m % d == 0)

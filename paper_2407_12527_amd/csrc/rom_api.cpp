@@ -202,9 +202,10 @@ struct Plan {
     std::vector<double> h_bt64;
     std::vector<uint16_t> h_bt16;
     int cells_per_block = 1024;
+    int many_cpt = 0;  // many-slot combine: cells per thread (0: the few-slot combine)
     // row-lane sweep
     int kind = ROM_SWEEP_STRIP;
-    int dR = 16, dK = 1, dNB = 1, wrap_cols = 0;
+    int dR = 16, dK = 1, dNB = 1;
     std::vector<DiagTaskDev> dtasks;
     DevMem d_dtasks;
 
@@ -236,9 +237,12 @@ struct Plan {
         a.ords = d_lanes.as<LaneDev>();
         a.probs = d_probs.as<ProblemDev>();
         a.sys = d_sys.as<SystemDev>();
+        a.tickets = d_tickets.as<int2>();
+        a.ntickets = ntickets;
         a.spin_limit = 1 << 24;
         a.mode_all = mode_all;
-        a.wrap_cols = wrap_cols;
+        a.edge = d_edge.p;
+        a.prog = d_prog.as<long long>();
         a.sigma_t = st_ptr();
         a.src = src_ptr();
         a.part = d_part.p;
@@ -252,7 +256,7 @@ struct Plan {
     // one sweep of every running system, with the plan's kernel
     hipError_t launch_sweep_any(int mode_all, hipStream_t s) const
     {
-        if (kind == ROM_SWEEP_DIAG) return launch_diag(diag_args(mode_all), (int)dtasks.size(), dNB, fp64, dR, dK, s);
+        if (kind == ROM_SWEEP_DIAG) return launch_diag(diag_args(mode_all), grid, dNB, fp64, dR, dK, s);
         return launch_sweep(sweep_args(mode_all, 0), grid, fp64, tx, ty, dd, aniso, aniso ? (fp64 ? 1 : 2) : 0, L, s);
     }
 
@@ -293,6 +297,7 @@ struct Plan {
         c.slot_off = d_slot_off.as<int64_t>();
         c.blocks = d_cblocks.as<int2>();
         c.cells_per_block = cells_per_block;
+        c.many_cpt = many_cpt;
         c.nsys = nsys;
         c.mode = mode;
         c.max_iter = max_iter;
@@ -388,8 +393,8 @@ bool has_inflow(rom_handle* h, const std::vector<SysInput>& in)
     return false;
 }
 
-// Row-lane sweep: unweighted inflow of every task ordinate on its entry faces, rows (x-face)
-// and columns (y-face) in sweep order, [position][NO].
+// Row-lane sweep: unweighted inflow of every task ordinate on its entry faces in sweep order:
+// x-face [row][NO], y-face [NO][pitch] (column runs per ordinate).
 std::vector<double> diag_inflow_table(const Plan& P, const std::vector<SysInput>& in)
 {
     const int NO = (kWave / P.dR) * P.dK;
@@ -418,7 +423,7 @@ std::vector<double> diag_inflow_table(const Plan& P, const std::vector<SysInput>
                 double v = 0.0;
                 if (angok && !h->ang[fy].empty()) v = h->ang[fy][(size_t)u * nx + i];
                 else if (!h->face[fy].empty()) v = h->face[fy][i];
-                inf[t.yin_off + (int64_t)ii * NO + k] = v;
+                inf[t.yin_off + (int64_t)k * diag_pitch(nx) + ii] = v;
             }
         }
     }
@@ -621,12 +626,17 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         int maxblocks = 1;
         for (auto& pd : P.probs) maxblocks = std::max(maxblocks, (pd.ny + R - 1) / R);
         const int nbmax = diag_max_nb(P.fp64, K);
-        P.dNB = o.band > 0 ? std::min(o.band, nbmax) : std::min(maxblocks, nbmax);
-        P.wrap_cols = 0;
-        for (auto& pd : P.probs)
-            if ((pd.ny + R - 1) / R > P.dNB) P.wrap_cols = std::max(P.wrap_cols, pd.nx);
-        if (diag_lds_bytes(P.fp64, R, K, P.dNB, P.wrap_cols) > 160 * 1024)
-            throw Fail{ROM_E_UNSUPPORTED, "row-lane sweep: rows too long for the LDS row buffer"};
+        int ntask = 0;
+        for (int sy = 0; sy < P.nsys; ++sy)
+            for (int q = 0; q < 4; ++q) ntask += ((int)ql[sy].idx[q].size() + NO - 1) / NO;
+        if (o.band > 0) {
+            P.dNB = std::min(o.band, nbmax);
+        } else {
+            // tall bands keep hand-offs in LDS; shorter ones put more workgroups on the CUs
+            P.dNB = std::min(maxblocks, nbmax);
+            while (P.dNB > 2 && (int64_t)ntask * ((maxblocks + P.dNB - 1) / P.dNB) < 2 * device_cus()) P.dNB /= 2;
+        }
+        if (diag_lds_bytes(P.fp64, R, K, P.dNB) > 64 * 1024) throw Fail{ROM_E_UNSUPPORTED, "row-lane sweep: LDS"};
         for (int sy = 0; sy < P.nsys; ++sy) {
             const int p = P.sys[sy].prob;
             rom_handle* h = P.handles[p];
@@ -643,12 +653,19 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
                     t.slot = P.nslots;
                     t.ord_off = (int64_t)P.lanes.size();
                     t.xin_off = t.yin_off = -1;
+                    const int pitch = diag_pitch(h->grid.nx);
                     if (inflow) {
                         t.xin_off = inflow_sum;
                         inflow_sum += (int64_t)h->grid.ny * NO;
+                        inflow_sum = (inflow_sum + 7) / 8 * 8;  // y-face runs are 16-byte vectors
                         t.yin_off = inflow_sum;
-                        inflow_sum += (int64_t)h->grid.nx * NO;
+                        inflow_sum += (int64_t)pitch * NO;
                     }
+                    const int nbands = ((h->grid.ny + R - 1) / R + P.dNB - 1) / P.dNB;
+                    t.edge_off = edge_sum;
+                    edge_sum += (int64_t)nbands * pitch * NO;
+                    t.prog_off = prog_sum;
+                    prog_sum += nbands;
                     for (int k = 0; k < NO; ++k) {
                         LaneDev ld{};
                         ld.ord = (int)uo.size();
@@ -755,13 +772,39 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
             if (bd < (P.probs[P.ws[k].prob].nstrips + P.band - 1) / P.band) P.tickets.push_back(make_int2(k, bd));
     P.ntickets = (int)P.tickets.size();
     P.grid = std::max(1, std::min(P.ntickets, device_cus() * 4));
-    if (P.kind == ROM_SWEEP_DIAG) P.grid = (int)P.dtasks.size();
-    // combine blocks: about 512 blocks per launch (each thread keeps 4 cells in flight)
+    if (P.kind == ROM_SWEEP_DIAG) {
+        // (task, band) tickets, band-major: the band below always holds an earlier ticket
+        P.tickets.clear();
+        int maxb = 0;
+        std::vector<int> nb_of(P.dtasks.size());
+        for (size_t k = 0; k < P.dtasks.size(); ++k) {
+            const int ny = P.probs[P.dtasks[k].prob].ny;
+            nb_of[k] = ((ny + P.dR - 1) / P.dR + P.dNB - 1) / P.dNB;
+            maxb = std::max(maxb, nb_of[k]);
+        }
+        for (int bd = 0; bd < maxb; ++bd)
+            for (size_t k = 0; k < P.dtasks.size(); ++k)
+                if (bd < nb_of[k]) P.tickets.push_back(make_int2((int)k, bd));
+        P.ntickets = (int)P.tickets.size();
+        P.grid = std::max(1, std::min(P.ntickets, device_cus() * std::max(1, kDiagMaxWaves / P.dNB)));
+    }
+    // combine blocks: with few slots per system, about 512 blocks per launch (each thread keeps
+    // 4 cells in flight); with many (the row-lane sweep's one slot per task), tiles of 64 * CPT
+    // cells whose four waves split the slot list, about four blocks per CU
     {
         int64_t tot = 0;
+        int maxslots = 0;
         for (auto& si : in) tot += si.h->cells;
-        int64_t cpb = (tot / 512 + 1023) / 1024 * 1024;
-        P.cells_per_block = (int)std::max<int64_t>(1024, std::min<int64_t>(cpb, 16384));
+        for (auto& sd : P.sys) maxslots = std::max(maxslots, sd.nslots);
+        P.many_cpt = 0;
+        if (maxslots > 8) {
+            P.many_cpt = 1;
+            while (P.many_cpt < 8 && tot / (64 * 2 * P.many_cpt) > 4 * device_cus()) P.many_cpt *= 2;
+            P.cells_per_block = 64 * P.many_cpt;
+        } else {
+            int64_t cpb = (tot / 512 + 1023) / 1024 * 1024;
+            P.cells_per_block = (int)std::max<int64_t>(1024, std::min<int64_t>(cpb, 16384));
+        }
     }
     for (int s = 0; s < P.nsys; ++s)
         for (int64_t c0 = 0; c0 < in[s].h->cells; c0 += P.cells_per_block) P.cblocks.push_back(make_int2(s, (int)c0));
@@ -1479,11 +1522,12 @@ void apply_choice(const TuneChoice& c, rom_si_opts& o)
     } else {
         o.diag_rows = c.rows;
         o.diag_k = c.k;
+        o.band = c.band;
     }
 }
 
-// Time three sweeps of every candidate on the real buffers of this batch shape (zero sources) and
-// keep the fastest for the process.  Candidates: the strip kernel's tiles x bands, and, for
+// Time three sweep + combine steps of every candidate on the real buffers of this batch shape
+// (zero sources) and keep the fastest for the process.  Candidates: the strip kernel's tiles x bands, and, for
 // isotropic step-scheme problems, the row-lane kernel's (rows, ordinates per lane).
 void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t s)
 {
@@ -1506,7 +1550,8 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t
         for (int rows : {16, 64})
             for (int k : {1, 2, 4})
                 if (diag_supported(fp64, rows, k) && (o.diag_rows == 0 || o.diag_rows == rows) && (o.diag_k == 0 || o.diag_k == k))
-                    cands.push_back({ROM_SWEEP_DIAG, 0, 0, 0, rows, k});
+                    for (int nb : rows == 16 ? std::vector<int>{4, 8, 16} : std::vector<int>{1, 2, 4})
+                        if (o.band == 0 || o.band == nb) cands.push_back({ROM_SWEEP_DIAG, 0, 0, nb, rows, k});
     }
     float best = 1e30f;
     TuneChoice pick;
@@ -1530,25 +1575,19 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t
         HIPCHK(launch_fill(P.src_ptr(), tot, P.fp64, 0.0, s));
         if (aniso) HIPCHK(launch_fill(P.d_ang.p, (int64_t)(P.d_ang.bytes / P.esz), P.fp64, 0.0, s));
         float ms = 0.f;
+        const CombineArgs ca = P.combine_args(1, 0.0);
         for (int rep = 0; rep < 3; ++rep) {
             HIPCHK(launch_reset_systems(P.d_sysctl.as<SysCtl>(), P.nsys, P.d_ctl.as<Ctl>(), s));
             if (rep == 1) HIPCHK(hipEventRecord(e0, s));
             HIPCHK(P.launch_sweep_any(1, s));
+            HIPCHK(launch_combine(ca, (int)P.cblocks.size(), P.fp64, s));  // a source-iteration step is both
         }
         HIPCHK(hipEventRecord(e1, s));
         HIPCHK(hipEventSynchronize(e1));
         HIPCHK(hipEventElapsedTime(&ms, e0, e1));
         Ctl ctl{};
         HIPCHK(hipMemcpy(&ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost));
-        // the row-lane kernel writes one partial slot per task: charge the combine step's extra
-        // reads (about 4 bytes per cell per slot at ~4 TB/s) so fewer, fuller slots can win
-        double extra = 0.0;
-        if (cand.sweep == ROM_SWEEP_DIAG) {
-            int64_t bytes = 0;
-            for (auto& sd : P.sys) bytes += (int64_t)sd.nslots * P.handles[sd.prob]->cells * P.esz;
-            extra = (double)bytes / 4.0e9;  // ms
-        }
-        const float score = ms + (float)extra;
+        const float score = ms;
         if (!ctl.error && score < best) {
             best = score;
             pick = cand;
@@ -1556,6 +1595,8 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t
                 pick.tx = P.tx;
                 pick.ty = P.ty;
                 pick.band = P.band;
+            } else {
+                pick.band = P.dNB;
             }
         }
     }
@@ -1577,7 +1618,7 @@ int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opt
     rom_si_opts o = o_in;
     if (reuse == 2 && slot && !refresh_ordinates(*slot, in, owner->stream())) reuse = 0;
     if (reuse == 0 || !slot) {
-        const bool free_shape = o.sweep == ROM_SWEEP_DIAG ? (o.diag_rows == 0 || o.diag_k == 0)
+        const bool free_shape = o.sweep == ROM_SWEEP_DIAG ? (o.diag_rows == 0 || o.diag_k == 0 || o.band == 0)
                                                           : (o.tile_x == 0 && o.band == 0);
         if (free_shape && autotune_enabled()) autotune(in, o, aniso, owner->stream());
         slot.reset(new Plan());

@@ -17,6 +17,7 @@
 // scalar-flux contribution is the plain lane sum and the anisotropic contraction multiplies by
 // P instead of W = w P (eq. (3.4)).
 #pragma once
+#include <hip/hip_runtime.h>
 #include <stdint.h>
 
 namespace rom {
@@ -62,19 +63,26 @@ struct SystemDev {
     int64_t ang_off;            // anisotropic source / angular flux [cells][npad] (elements)
 };
 
-// Task of the row-lane ("diagonal") sweep: one workgroup sweeps the whole grid of one problem for
-// NO = (64 / R) * K ordinates of one quadrant of one system.  Lane g*R + r holds row r of an
-// R-row block for ordinates g*K .. g*K + K - 1 (the group's entries ord_off + g*K + k of the lane
-// table).  Its wavefronts take the row blocks in turn (block b -> wave b mod NB).
+// Task of the row-lane ("diagonal") sweep: the whole grid of one problem for NO = (64 / R) * K
+// ordinates of one quadrant of one system, swept band by band (NB row blocks of R rows per band,
+// one workgroup per band).  Lane g*R + r holds row r of an R-row block for ordinates
+// g*K .. g*K + K - 1 (the task's entries ord_off + g*K + k of the lane table).
 constexpr int kDiagMaxWaves = 16;
 constexpr int kPoolPad = 128;   // elements of padding before and after the sigma_t and source pools
+
+// Row pitch (elements) of the row-lane sweep's y-face tables and band edges: a multiple of 8
+// with at least 8 elements of padding, so U-column runs past the row end stay inside.
+__host__ __device__ inline int diag_pitch(int nx) { return ((nx + 7) & ~7) + 8; }
 
 struct DiagTaskDev {
     int32_t sys, prob, quad;
     int32_t slot;               // partial-flux slot
     int64_t ord_off;            // first of the task's NO lane-table entries
     int64_t xin_off;            // inflow on the entry x-face [ny][NO], rows in sweep order; -1 vacuum
-    int64_t yin_off;            // inflow on the entry y-face [nx][NO], columns in sweep order; -1 vacuum
+    int64_t yin_off;            // inflow on the entry y-face [NO][pitch], columns in sweep order; -1 vacuum
+    int64_t edge_off;           // top rows of its bands [nbands][NO][pitch] (elements of T)
+    int32_t prog_off;           // first of its per-band progress counters
+    int32_t pad;
 };
 
 // Per-system convergence state, written only by the combine step.

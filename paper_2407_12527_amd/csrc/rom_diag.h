@@ -13,12 +13,12 @@
 //   each lane carries K ordinates of its slot (independent chains, for instruction-level
 //   parallelism), so a wavefront covers NO = (64 / R) * K ordinates of one quadrant.
 //
-// A workgroup of NB wavefronts owns one task (system, quadrant, NO ordinates) and the whole grid:
-// wave w takes row blocks w, w + NB, w + 2 NB, ...  A block's top row goes to the block above
-// through LDS: a ring of RING columns between waves w and w + 1 of the same round (with
-// back-pressure), and a whole-row buffer from the last wave to wave 0 of the next round (no
-// back-pressure is needed there: the next round's writer depends on the reader through the chain
-// of blocks between them).  Waits are bounded and record an error instead of hanging.
+// A task is (system, quadrant, NO ordinates) over the whole grid; its row blocks are cut into
+// bands of NB consecutive blocks, and a workgroup of NB wavefronts sweeps one band (wave w takes
+// block band * NB + w).  Inside a band a block's top row goes to the block above through an LDS
+// ring of RING columns (produced / consumed counters, back-pressure); the band's top row goes to
+// the next band through a global edge buffer behind an epoch-tagged progress counter.  Waits are
+// bounded and record an error instead of hanging.
 //
 // The field and source pools carry kPoolPad elements of padding on both sides, so the skewed
 // loads of lanes before or past their row need no clamping.
@@ -39,9 +39,10 @@ template <int R>
 constexpr int diag_ring() { return R == 16 ? 64 : 128; }
 template <typename T>
 constexpr int diag_unroll() { return sizeof(T) == 8 ? 4 : 8; }
-// most wavefronts per workgroup: 16, or 8 where the lane state needs more than 128 VGPRs
-template <typename T, int K>
-constexpr int diag_max_waves() { return (K * sizeof(T) >= 16) ? 8 : kDiagMaxWaves; }
+// Most wavefronts per workgroup: 16, or 8 where the lane state needs more than 128 VGPRs (more
+// than one ordinate per lane, or loads kept PD = 2 blocks ahead).
+template <typename T, int K, int PD>
+constexpr int diag_max_waves() { return (PD > 1 || K > 1) ? 8 : kDiagMaxWaves; }
 
 // lane r of each R-lane block takes lane r - 1's v; lane 0 of the block keeps `old`
 template <int R>
@@ -97,12 +98,46 @@ __device__ __forceinline__ void slot_sums(const T (&acc)[U], T (&out)[U / 4])
     for (int v = 0; v < U / 4; ++v) out[v] = halve_swap<16>(h[v], h[v + U / 4]);
 }
 
-// Bounded wait on an LDS counter; returns the value seen (cached by the caller).
+// LDS hand-off counters between the wavefronts of a workgroup.  A wave's LDS operations complete
+// in issue order and LDS is one coherent memory per CU, so publishing needs only the wave's own
+// LDS traffic drained (s_waitcnt lgkmcnt(0)) -- not its global loads and stores, which a
+// memory-model release at workgroup scope would also wait for.
+__device__ __forceinline__ void lds_publish(int* p, int v)
+{
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    *(volatile int*)p = v;
+}
+
+// Bounded wait on an LDS counter; returns the value seen (cached by the caller).  Reads that
+// follow stay after the poll (compiler barrier; LDS answers a wave's reads in order).
 __device__ __forceinline__ int lds_wait_get(int* p, int target, Ctl* ctl, int limit)
 {
     int spins = 0;
     int v;
-    while ((v = __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP)) < target) {
+    while ((v = *(volatile int*)p) < target) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins >= limit) {
+            __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            v = target;
+            break;
+        }
+        if ((spins & 1023) == 0 &&
+            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
+            v = target;
+            break;
+        }
+    }
+    asm volatile("" ::: "memory");
+    return v;
+}
+
+// Bounded wait on a device-scope progress counter (another workgroup's band); returns the value
+// seen.  The counter carries the sweep's epoch in its high bits.
+__device__ __forceinline__ long long wait_progress_get(long long* p, long long target, Ctl* ctl, int limit)
+{
+    int spins = 0;
+    long long v;
+    while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
         __builtin_amdgcn_s_sleep(1);
         if (++spins >= limit) {
             __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
@@ -112,23 +147,104 @@ __device__ __forceinline__ int lds_wait_get(int* p, int target, Ctl* ctl, int li
             __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
             return target;
     }
+    asm volatile("" ::: "memory");  // edge loads stay after the poll
     return v;
 }
 
-// Everything one task needs, read once per workgroup (uniform values).
+// Everything one (task, band) needs, read once per workgroup (uniform values).
 template <typename T>
 struct DiagTask {
-    int nx, ny, nblocks;
+    int nx, ny, nblocks, pitch;
     bool ypos;
-    const T* st;       // sigma_t of the problem (pool padded by kPoolPad elements on both sides)
-    const T* S;        // isotropic source of the system (same padding)
-    T* part;           // partial-flux slot
+    const T* st;         // sigma_t of the problem (pool padded by kPoolPad elements on both sides)
+    const T* S;          // isotropic source of the system (same padding)
+    T* part;             // partial-flux slot
     const T* inflow;
-    int64_t xin, yin;  // inflow tables, -1 for vacuum
+    int64_t xin, yin;    // inflow tables, -1 for vacuum
+    const T* edge_in;    // top row of the band below [NO][pitch] (global), its progress counter
+    long long* prog_in;
+    T* edge_out;         // this band's top row for the band above, and its progress counter
+    long long* prog_out;
+    long long tag;       // sweep epoch << 24
 };
 
-template <typename T, int R, int K, bool XPOS>
-__device__ __forceinline__ void diag_sweep(const DiagArgs& A, const DiagTask<T>& D, T* ring, T* wrap, T* scratch, int* prod, int* cons,
+// U consecutive values at p (16-byte aligned) as 16-byte LDS or global accesses.
+template <typename T, int U>
+__device__ __forceinline__ void load_run(const T* p, T (&v)[U])
+{
+    constexpr int W = 16 / sizeof(T);
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+#pragma unroll
+    for (int q = 0; q < U / W; ++q) {
+        const V x = reinterpret_cast<const V*>(p)[q];
+        const T* e = reinterpret_cast<const T*>(&x);
+#pragma unroll
+        for (int m = 0; m < W; ++m) v[q * W + m] = e[m];
+    }
+}
+
+template <typename T, int U>
+__device__ __forceinline__ void store_run(T* p, const T (&v)[U])
+{
+    constexpr int W = 16 / sizeof(T);
+    using V = typename std::conditional<sizeof(T) == 4, float4, double2>::type;
+#pragma unroll
+    for (int q = 0; q < U / W; ++q) {
+        V x;
+        T* e = reinterpret_cast<T*>(&x);
+#pragma unroll
+        for (int m = 0; m < W; ++m) e[m] = v[q * W + m];
+        reinterpret_cast<V*>(p)[q] = x;
+    }
+}
+
+// Device-coherent runs for the band edges (8-byte relaxed agent-scope accesses: the producer and
+// the consumer band may sit on different XCDs).
+template <typename T, int U>
+__device__ __forceinline__ void load_run_agent(const T* p, T (&v)[U])
+{
+    constexpr int W = 8 / sizeof(T);
+#pragma unroll
+    for (int q = 0; q < U / W; ++q) {
+        const unsigned long long x =
+            __hip_atomic_load(reinterpret_cast<const unsigned long long*>(p) + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        const T* e = reinterpret_cast<const T*>(&x);
+#pragma unroll
+        for (int m = 0; m < W; ++m) v[q * W + m] = e[m];
+    }
+}
+
+template <typename T, int U>
+__device__ __forceinline__ void store_run_agent(T* p, const T (&v)[U])
+{
+    constexpr int W = 8 / sizeof(T);
+#pragma unroll
+    for (int q = 0; q < U / W; ++q) {
+        unsigned long long x;
+        T* e = reinterpret_cast<T*>(&x);
+#pragma unroll
+        for (int m = 0; m < W; ++m) e[m] = v[q * W + m];
+        __hip_atomic_store(reinterpret_cast<unsigned long long*>(p) + q, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+}
+
+// Where a block's top row goes (nowhere: top block of the grid; the LDS ring of the next wave;
+// the band's global edge) and where its bottom row's y-face inflow comes from (the LDS ring of the
+// previous wave; the boundary inflow table; the global edge of the band below).  Both are template
+// parameters so a wave that only talks to LDS never waits on its global loads and stores.
+enum { kOutNone = 0, kOutRing = 1, kOutEdge = 2 };
+enum { kInRing = 0, kInBoundary = 1, kInEdge = 2 };
+
+// One R-row block (row block rb, wavefront `wave` of an NB-wave band) of one task.
+//
+// Hand-off layout: rings are [NO][RING] and edges [NO][pitch] (columns contiguous per ordinate),
+// so a block of U steps reads its U input columns and writes its U output columns as runs.  The
+// top row of column c leaves the lane of row R - 1 at step c + R - 1; block t0 exports columns
+// t0 - R .. t0 - R + U - 1 (the previous block's last value and this block's first U - 1), so
+// every run is U-aligned.
+template <typename T, int R, int K, int PD, bool XPOS, int IN, int OUT>
+__device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>& D, const int rb, const int wave,
+                                           T* ring, int* prod, int* cons,
                                            const T (&a)[K], const T (&b)[K], const T (&ab)[K], const T (&w)[K])
 {
     constexpr int NG = kWave / R;
@@ -136,167 +252,231 @@ __device__ __forceinline__ void diag_sweep(const DiagArgs& A, const DiagTask<T>&
     constexpr int U = diag_unroll<T>();
     constexpr int RING = diag_ring<R>();
     constexpr int DIR = XPOS ? 1 : -1;  // storage step per sweep column
-    const int wave = uniform(threadIdx.x >> 6);
+    static_assert(RING % U == 0 && R % U == 0, "runs must stay aligned");
     const int lane = threadIdx.x & (kWave - 1);
-    const int NB = blockDim.x >> 6;
     const int g = lane / R, r = lane % R;
     const int nx = D.nx, ny = D.ny;
 
-    for (int rb = wave; rb < D.nblocks; rb += NB) {
-        const int round = rb / NB;
-        const int jj = rb * R + r;               // sweep-order row of this lane
-        const bool row_ok = jj < ny;
-        const int jc = min(jj, ny - 1);
-        const int j = D.ypos ? jc : ny - 1 - jc;
-        // storage index of this lane's cell at step t is lane0 + DIR * t
-        const int64_t lane0 = (int64_t)j * nx + (XPOS ? -r : nx - 1 + r);
-        const bool has_out = rb + 1 < D.nblocks;   // only the last block may be partial
-        const bool in_bc = rb == 0;
-        const bool in_wrap = !in_bc && wave == 0;
-        const T* in_buf = in_wrap ? wrap : ring + (size_t)(wave > 0 ? wave - 1 : 0) * RING * NO;
-        int* in_cnt = in_wrap ? &prod[NB - 1] : &prod[wave > 0 ? wave - 1 : 0];
-        const int in_base = in_wrap ? (round - 1) * nx : round * nx;
-        const unsigned in_mask = in_wrap ? 0x7fffffffu : (unsigned)(RING - 1);
-        const int in_off = in_wrap ? 0 : in_base;
-        const bool out_wrap = wave == NB - 1;
-        T* out_buf = out_wrap ? wrap : ring + (size_t)wave * RING * NO;
-        const int out_base = round * nx;
-        const unsigned out_mask = out_wrap ? 0x7fffffffu : (unsigned)(RING - 1);
-        const int out_off = out_wrap ? 0 : out_base;
-        int seen_in = 0, seen_out = 0;
-        // Interior steps export without exec-mask changes: the exporting lanes (row R - 1 of a
-        // block that has a block above) address the ring, every other lane a scratch slot.
-        const bool exp_lane = has_out && r == R - 1;
-        const unsigned exp_stride = exp_lane ? (unsigned)(NO * sizeof(T)) : 0u;
-        const unsigned exp_base = exp_lane ? (unsigned)((const char*)(out_buf + g * K) - (const char*)ring)
-                                           : (unsigned)((const char*)(scratch + lane * K) - (const char*)ring);
+    const int jj = rb * R + r;               // sweep-order row of this lane
+    const bool row_ok = jj < ny;
+    const int jc = min(jj, ny - 1);
+    const int j = D.ypos ? jc : ny - 1 - jc;
+    // storage index of this lane's cell at step t is lane0 + DIR * t
+    const int64_t lane0 = (int64_t)j * nx + (XPOS ? -r : nx - 1 + r);
+    constexpr bool in_bc = IN == kInBoundary;
+    constexpr bool in_glob = IN == kInEdge;
+    const T* in_ring = ring + (size_t)(wave > 0 ? wave - 1 : 0) * RING * NO;
+    T* out_ring = ring + (size_t)wave * RING * NO;
+    long long seen_in = 0;
+    int seen_out = 0;
 
-        T psi[K];
+    T psi[K], last[K];
 #pragma unroll
-        for (int k = 0; k < K; ++k)
-            psi[k] = (D.xin >= 0 && row_ok) ? D.inflow[D.xin + (int64_t)jc * NO + g * K + k] : T(0);
+    for (int k = 0; k < K; ++k) {
+        psi[k] = (D.xin >= 0 && row_ok) ? D.inflow[D.xin + (int64_t)jc * NO + g * K + k] : T(0);
+        last[k] = T(0);
+    }
 
-        T pst[U], pS[U];
-        // cells of steps t0 .. t0 + U - 1; lanes before or past their row read padding or a
-        // neighbouring row, values that never reach a stored or exported result
-        auto fetch = [&](int t0) {
-            const int64_t c0 = lane0 + (int64_t)DIR * t0;
+    // cells of steps t0 .. t0 + U - 1; lanes before or past their row read padding or a
+    // neighbouring row, values that never reach a stored or exported result.  PD register sets
+    // keep the loads PD blocks ahead of their use.
+    T pst[PD][U], pS[PD][U];
+    auto fetch = [&](T (&fst)[U], T (&fS)[U], int t0) {
+        const int64_t c0 = lane0 + (int64_t)DIR * t0;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                pst[u] = D.st[c0 + DIR * u];
-                pS[u] = D.S[c0 + DIR * u];
-            }
-        };
-        const int tsteps = nx + R - 1;
-        fetch(0);
-        for (int t0 = 0; t0 < tsteps; t0 += U) {
-            T cst[U], cS[U];
+        for (int u = 0; u < U; ++u) {
+            fst[u] = D.st[c0 + DIR * u];
+            fS[u] = D.S[c0 + DIR * u];
+        }
+    };
+    const int tsteps = nx + R - 1;                          // steps with a cell in the block
+    const int tend = R + U * ((nx + U - 1) / U);            // ... and until the last column is exported
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                cst[u] = pst[u];
-                cS[u] = pS[u];
-            }
-            if (t0 + U < tsteps) fetch(t0 + U);
+    for (int q = 0; q < PD; ++q)
+        if (q * U < tsteps) fetch(pst[q], pS[q], q * U);
 
-            // y-face inflow of row 0 for columns t0 .. t0 + U - 1 (used by row 0 only, and only
-            // for columns < nx; later reads are clamped to a valid entry)
-            T in[U][K];
-            const int cin_hi = min(t0 + U, nx);
-            if (in_bc) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int c = min(t0 + u, nx - 1);
-#pragma unroll
-                    for (int k = 0; k < K; ++k) in[u][k] = D.yin >= 0 ? D.inflow[D.yin + (int64_t)c * NO + g * K + k] : T(0);
-                }
-            } else {
-                if (t0 < nx && seen_in < in_base + cin_hi) seen_in = lds_wait_get(in_cnt, in_base + cin_hi, A.ctl, A.spin_limit);
-#pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    const int c = min(t0 + u, nx - 1);
-                    const int pos = (int)((unsigned)(in_off + c) & in_mask);
-#pragma unroll
-                    for (int k = 0; k < K; ++k) in[u][k] = in_buf[pos * NO + g * K + k];
-                }
-            }
-            // room in the ring for the top-row columns of this block of steps
-            const int cout_hi = min(t0 + U - R, nx - 1);
-            if (has_out && !out_wrap && cout_hi >= 0) {
-                const int need = out_base + cout_hi + 1 - RING;
-                if (need > 0 && seen_out < need) seen_out = lds_wait_get(&cons[wave], need, A.ctl, A.spin_limit);
-            }
-
-            // MODE 0: every lane inside its row; 1: lanes before their row start hold their
-            // x-face inflow; 2: lanes outside their row store nothing
-            T acc[U];
-            auto step = [&](const int u, auto mode) {
-                constexpr int MODE = decltype(mode)::value;
-                const int c = t0 + u - r;
+    auto block = [&](const int t0, const T (&cst)[U], const T (&cS)[U]) {
+        // y-face inflow of row 0 for columns t0 .. t0 + U - 1 (only row 0 uses it, and only for
+        // columns < nx; the runs reach into the tables' padding past the row end)
+        T in[K][U];
+        const int cin_hi = min(t0 + U, nx);
+        if (t0 < nx) {
+            if constexpr (in_bc) {
 #pragma unroll
                 for (int k = 0; k < K; ++k) {
-                    const T dn = shift_up<R>(in[u][k], psi[k]);
-                    const T num = fma(b[k], dn, fma(a[k], psi[k], cS[u]));
-                    const T v = num * rcp_fast(cst[u] + ab[k]);
-                    if (MODE == 1) psi[k] = c >= 0 ? v : psi[k];
-                    else psi[k] = v;
-                    acc[u] = k == 0 ? w[k] * v : fma(w[k], v, acc[u]);
+                    if (D.yin >= 0) load_run<T, U>(D.inflow + D.yin + (int64_t)(g * K + k) * D.pitch + t0, in[k]);
+                    else {
+#pragma unroll
+                        for (int u = 0; u < U; ++u) in[k][u] = T(0);
+                    }
                 }
-                // the exporting lanes (row R - 1) share one column: a uniform position
-                const int cx = t0 + u - (R - 1);
-                const unsigned pos = (unsigned)(out_off + cx) & out_mask;
-                if constexpr (MODE == 0) {
-                    T* const p = (T*)((char*)ring + (__umul24(pos, exp_stride) + exp_base));
+            } else if constexpr (in_glob) {
+                if (seen_in < (D.tag | cin_hi)) seen_in = wait_progress_get(D.prog_in, D.tag | cin_hi, A.ctl, A.spin_limit);
 #pragma unroll
-                    for (int k = 0; k < K; ++k) p[k] = psi[k];
-                } else if (has_out && cx >= 0 && cx < nx && r == R - 1) {
-#pragma unroll
-                    for (int k = 0; k < K; ++k) out_buf[pos * NO + g * K + k] = psi[k];
-                }
-            };
-            const int mode = t0 < R ? 1 : (t0 + U <= nx ? 0 : 2);
-            if (mode == 0) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) step(u, std::integral_constant<int, 0>{});
-            } else if (mode == 1) {
-#pragma unroll
-                for (int u = 0; u < U; ++u) step(u, std::integral_constant<int, 1>{});
+                for (int k = 0; k < K; ++k) load_run_agent<T, U>(D.edge_in + (int64_t)(g * K + k) * D.pitch + t0, in[k]);
             } else {
+                if (seen_in < cin_hi) seen_in = lds_wait_get(&prod[wave - 1], cin_hi, A.ctl, A.spin_limit);
 #pragma unroll
-                for (int u = 0; u < U; ++u) step(u, std::integral_constant<int, 2>{});
+                for (int k = 0; k < K; ++k) load_run<T, U>(in_ring + (g * K + k) * RING + (t0 & (RING - 1)), in[k]);
             }
-            // partial scalar flux of the block's cells
-            T* const pblk = D.part + lane0 + (int64_t)DIR * t0;
-            if constexpr (NG == 4) {
-                T tot[U / 4];
-                slot_sums<T, U>(acc, tot);
+        } else {
+#pragma unroll
+            for (int k = 0; k < K; ++k)
+#pragma unroll
+                for (int u = 0; u < U; ++u) in[k][u] = T(0);
+        }
+        // room in the ring for this block's run of top-row columns
+        const int c_out = t0 - R;  // first exported column
+        if (OUT == kOutRing && c_out + U > 0) {
+            const int need = c_out + U - RING;
+            if (need > 0 && seen_out < need) seen_out = lds_wait_get(&cons[wave], need, A.ctl, A.spin_limit);
+        }
+
+        // MODE 0: every lane inside its row; 1: lanes before their row start hold their x-face
+        // inflow; 2: lanes outside their row store nothing
+        T acc[U];
+        T hist[K][U];
+        auto step = [&](const int u, auto mode) {
+            constexpr int MODE = decltype(mode)::value;
+            const int c = t0 + u - r;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                const T dn = shift_up<R>(in[k][u], psi[k]);
+                const T num = fma(b[k], dn, fma(a[k], psi[k], cS[u]));
+                const T v = num * rcp_fast(cst[u] + ab[k]);
+                if (MODE == 1) psi[k] = c >= 0 ? v : psi[k];
+                else psi[k] = v;
+                hist[k][u] = psi[k];
+                acc[u] = k == 0 ? w[k] * v : fma(w[k], v, acc[u]);
+            }
+        };
+        const int mode = t0 < R ? 1 : (t0 + U <= nx ? 0 : 2);
+        if (mode == 0) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) step(u, std::integral_constant<int, 0>{});
+        } else if (mode == 1) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) step(u, std::integral_constant<int, 1>{});
+        } else {
+#pragma unroll
+            for (int u = 0; u < U; ++u) step(u, std::integral_constant<int, 2>{});
+        }
+
+        // export columns c_out .. c_out + U - 1 from the top row
+        if (OUT != kOutNone && r == R - 1 && c_out + U > 0 && c_out < nx) {
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                T run[U];
+                run[0] = last[k];
+#pragma unroll
+                for (int u = 1; u < U; ++u) run[u] = hist[k][u - 1];
+                if (c_out >= 0 && c_out + U <= nx) {
+                    if (OUT == kOutRing) store_run<T, U>(out_ring + (g * K + k) * RING + (c_out & (RING - 1)), run);
+                    else store_run_agent<T, U>(D.edge_out + (int64_t)(g * K + k) * D.pitch + c_out, run);
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) {
+                        const int c = c_out + u;
+                        if (c >= 0 && c < nx) {
+                            if (OUT == kOutRing) out_ring[(g * K + k) * RING + (c & (RING - 1))] = run[u];
+                            else edge_store(D.edge_out + (int64_t)(g * K + k) * D.pitch + c, run[u]);
+                        }
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int k = 0; k < K; ++k) last[k] = hist[k][U - 1];
+
+        // partial scalar flux of the block's cells
+        T* const pblk = D.part + lane0 + (int64_t)DIR * t0;
+        if constexpr (NG == 4) {
+            T tot[U / 4];
+            slot_sums<T, U>(acc, tot);
+            if (mode == 0) {
+                if (row_ok) {
+#pragma unroll
+                    for (int v = 0; v < U / 4; ++v) pblk[DIR * (v + g * (U / 4))] = tot[v];
+                }
+            } else {
 #pragma unroll
                 for (int v = 0; v < U / 4; ++v) {
                     const int u = v + g * (U / 4);
                     const int c = t0 + u - r;
-                    if (row_ok && (mode == 0 || (c >= 0 && c < nx))) pblk[DIR * u] = tot[v];
+                    if (row_ok && c >= 0 && c < nx) pblk[DIR * u] = tot[v];
+                }
+            }
+        } else {
+            if (mode == 0) {
+                if (row_ok) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) pblk[DIR * u] = acc[u];
                 }
             } else {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     const int c = t0 + u - r;
-                    if (row_ok && (mode == 0 || (c >= 0 && c < nx))) pblk[DIR * u] = acc[u];
+                    if (row_ok && c >= 0 && c < nx) pblk[DIR * u] = acc[u];
                 }
             }
+        }
 
-            if (lane == 0) {
-                if (!in_bc && !in_wrap && t0 < nx)
-                    __hip_atomic_store(&cons[wave - 1], in_base + cin_hi, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
-                if (has_out) {
-                    const int done = min(max(t0 + U - R + 1, 0), nx);
-                    __hip_atomic_store(&prod[wave], out_base + done, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
+        const int done = min(max(c_out + U, 0), nx);   // top-row columns exported so far
+        if (OUT == kOutEdge) stores_complete();         // the edge words have landed before publishing
+        if (lane == 0) {
+            if (!in_bc && !in_glob && t0 < nx)
+                lds_publish(&cons[wave - 1], cin_hi);
+            if (OUT == kOutEdge)
+                __hip_atomic_store(D.prog_out, D.tag | done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            else if (OUT == kOutRing)
+                lds_publish(&prod[wave], done);
+        }
+    };
+
+    for (int t0 = 0; t0 < tend; t0 += PD * U) {
+#pragma unroll
+        for (int q = 0; q < PD; ++q) {
+            const int tq = t0 + q * U;
+            if (q == 0 || tq < tend) {
+                T cst[U], cS[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    cst[u] = pst[q][u];
+                    cS[u] = pS[q][u];
                 }
+                if (tq + PD * U < tsteps) fetch(pst[q], pS[q], tq + PD * U);
+                block(tq, cst, cS);
             }
         }
     }
 }
 
-template <typename T, int R, int K>
-__global__ __launch_bounds__((64 * diag_max_waves<T, K>())) void diag_kernel(DiagArgs A)
+template <typename T, int R, int K, int PD, bool XPOS>
+__device__ __forceinline__ void diag_block_any(const DiagArgs& A, const DiagTask<T>& D, const int rb, const int wave, const int NB,
+                                               T* ring, int* prod, int* cons,
+                                               const T (&a)[K], const T (&b)[K], const T (&ab)[K], const T (&w)[K])
+{
+    const int out = rb + 1 >= D.nblocks ? kOutNone : (wave == NB - 1 ? kOutEdge : kOutRing);
+    if (rb == 0) {
+        if (out == kOutNone) diag_block<T, R, K, PD, XPOS, kInBoundary, kOutNone>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else if (out == kOutEdge) diag_block<T, R, K, PD, XPOS, kInBoundary, kOutEdge>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else diag_block<T, R, K, PD, XPOS, kInBoundary, kOutRing>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+    } else if (wave == 0) {
+        if (out == kOutNone) diag_block<T, R, K, PD, XPOS, kInEdge, kOutNone>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else if (out == kOutEdge) diag_block<T, R, K, PD, XPOS, kInEdge, kOutEdge>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else diag_block<T, R, K, PD, XPOS, kInEdge, kOutRing>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+    } else {
+        if (out == kOutNone) diag_block<T, R, K, PD, XPOS, kInRing, kOutNone>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else if (out == kOutEdge) diag_block<T, R, K, PD, XPOS, kInRing, kOutEdge>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else diag_block<T, R, K, PD, XPOS, kInRing, kOutRing>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+    }
+}
+
+// Persistent workgroups take (task, band) tickets in band-major order, so the band below a
+// ticket's band always holds an earlier ticket: every wait is on a workgroup that is running or
+// done.
+template <typename T, int R, int K, int PD>
+__global__ __launch_bounds__((64 * diag_max_waves<T, K, PD>())) void diag_kernel(DiagArgs A)
 {
     constexpr int NG = kWave / R;
     constexpr int NO = NG * K;
@@ -307,65 +487,83 @@ __global__ __launch_bounds__((64 * diag_max_waves<T, K>())) void diag_kernel(Dia
     const int g = lane / R;
 
     extern __shared__ __align__(16) unsigned char smem[];
-    T* const ring = (T*)smem;                                        // [NB - 1][RING][NO]
-    T* const wrap = ring + (size_t)(NB - 1) * RING * NO;            // [wrap_cols][NO]
-    T* const scratch = wrap + (size_t)A.wrap_cols * NO;              // [64][K], write-only
-    int* const prod = (int*)(scratch + kWave * K);                   // [kDiagMaxWaves]
+    T* const ring = (T*)smem;                                        // [NB - 1][NO][RING]
+    int* const prod = (int*)(ring + (size_t)(NB - 1) * RING * NO);   // [kDiagMaxWaves]
     int* const cons = prod + kDiagMaxWaves;
+    int& s_ticket = cons[kDiagMaxWaves];
 
-    const DiagTaskDev& TK = A.tasks[blockIdx.x];
-    const int sys = uniform(TK.sys);
-    if (!A.mode_all && uniform(A.sysctl[sys].state) != 0) return;   // uniform over the workgroup
+    if (!A.mode_all && A.ctl->active == 0) return;   // every system has stopped
     if (threadIdx.x == 0) atomicMin(&A.ctl->t_first, (unsigned long long)wall_clock64());
-    if (lane == 0) {
-        prod[wave] = 0;
-        cons[wave] = 0;
-    }
-    __syncthreads();
-
-    const int prob = uniform(TK.prob), quad = uniform(TK.quad), slot = uniform(TK.slot);
-    const int64_t ord_off = uniform64(TK.ord_off);
-    const ProblemDev& PD = A.probs[prob];
-    DiagTask<T> D;
-    D.nx = uniform(PD.nx);
-    D.ny = uniform(PD.ny);
-    D.nblocks = (D.ny + R - 1) / R;
-    D.ypos = quad < 2;
-    D.st = (const T*)A.sigma_t + uniform64(PD.field_off);
-    D.S = (const T*)A.src + uniform64(A.sys[sys].src_off);
-    D.part = (T*)A.part + A.slot_off[slot];
-    D.inflow = (const T*)A.inflow;
-    D.xin = uniform64(TK.xin_off);
-    D.yin = uniform64(TK.yin_off);
-
-    T a[K], b[K], ab[K], w[K];
+    const long long tag = (long long)uniform(A.ctl->epoch) << 24;
+    for (;;) {
+        if (threadIdx.x == 0) s_ticket = atomicAdd(&A.ctl->ticket, 1);
+        if (lane == 0) {
+            prod[wave] = 0;
+            cons[wave] = 0;
+        }
+        __syncthreads();
+        const int t = s_ticket;
+        if (t >= A.ntickets) break;  // uniform over the workgroup
+        const int2 tk = A.tickets[t];
+        const DiagTaskDev& TK = A.tasks[uniform(tk.x)];
+        const int band = uniform(tk.y);
+        const int sys = uniform(TK.sys);
+        if (A.mode_all || uniform(A.sysctl[sys].state) == 0) {
+            const int prob = uniform(TK.prob), quad = uniform(TK.quad), slot = uniform(TK.slot);
+            const int64_t ord_off = uniform64(TK.ord_off);
+            const ProblemDev& PB = A.probs[prob];
+            DiagTask<T> D;
+            D.nx = uniform(PB.nx);
+            D.ny = uniform(PB.ny);
+            D.pitch = diag_pitch(D.nx);
+            D.nblocks = (D.ny + R - 1) / R;
+            D.ypos = quad < 2;
+            D.st = (const T*)A.sigma_t + uniform64(PB.field_off);
+            D.S = (const T*)A.src + uniform64(A.sys[sys].src_off);
+            D.part = (T*)A.part + A.slot_off[slot];
+            D.inflow = (const T*)A.inflow;
+            D.xin = uniform64(TK.xin_off);
+            D.yin = uniform64(TK.yin_off);
+            const int64_t eoff = uniform64(TK.edge_off), edge_len = (int64_t)D.pitch * NO;
+            const int poff = uniform(TK.prog_off);
+            D.edge_in = (const T*)A.edge + eoff + (int64_t)(band - 1) * edge_len;
+            D.prog_in = A.prog + poff + band - 1;
+            D.edge_out = (T*)A.edge + eoff + (int64_t)band * edge_len;
+            D.prog_out = A.prog + poff + band;
+            D.tag = tag;
+            const int rb = band * NB + wave;
+            if (rb < D.nblocks) {
+                T a[K], b[K], ab[K], w[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        const LaneDev& o = A.ords[ord_off + g * K + k];
-        a[k] = to_T<T>(o.a);
-        b[k] = to_T<T>(o.b);
-        ab[k] = a[k] + b[k];
-        w[k] = to_T<T>(o.w);
+                for (int k = 0; k < K; ++k) {
+                    const LaneDev& o = A.ords[ord_off + g * K + k];
+                    a[k] = to_T<T>(o.a);
+                    b[k] = to_T<T>(o.b);
+                    ab[k] = a[k] + b[k];
+                    w[k] = to_T<T>(o.w);
+                }
+                if (quad == 0 || quad == 3) diag_block_any<T, R, K, PD, true>(A, D, rb, wave, NB, ring, prod, cons, a, b, ab, w);
+                else diag_block_any<T, R, K, PD, false>(A, D, rb, wave, NB, ring, prod, cons, a, b, ab, w);
+            }
+        }
+        __syncthreads();  // the band is done before its LDS is reused
     }
-    if (quad == 0 || quad == 3) diag_sweep<T, R, K, true>(A, D, ring, wrap, scratch, prod, cons, a, b, ab, w);
-    else diag_sweep<T, R, K, false>(A, D, ring, wrap, scratch, prod, cons, a, b, ab, w);
     if (lane == 0) atomicMax(&A.ctl->t_last, (unsigned long long)wall_clock64());
 }
 
-template <typename T, int R, int K>
-hipError_t launch_diag_t(const DiagArgs& a, int ntasks, int nb, hipStream_t s)
+template <typename T, int R, int K, int PD>
+hipError_t launch_diag_t(const DiagArgs& a, int grid, int nb, hipStream_t s)
 {
     constexpr int NO = (kWave / R) * K;
-    if (nb < 1 || nb > diag_max_waves<T, K>() || ntasks < 1) return hipErrorInvalidValue;
-    const size_t lds = sizeof(T) * (((size_t)(nb - 1) * diag_ring<R>() + (size_t)a.wrap_cols) * NO + kWave * K) +
-                       sizeof(int) * 2 * kDiagMaxWaves;
+    if (nb < 1 || nb > diag_max_waves<T, K, PD>() || grid < 1) return hipErrorInvalidValue;
+    const size_t lds = sizeof(T) * (size_t)(nb - 1) * diag_ring<R>() * NO + sizeof(int) * (2 * kDiagMaxWaves + 1);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute((const void*)diag_kernel<T, R, K>,
+        const hipError_t e = hipFuncSetAttribute((const void*)diag_kernel<T, R, K, PD>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((diag_kernel<T, R, K>), dim3(ntasks), dim3(64 * nb), lds, s, a);
+    hipLaunchKernelGGL((diag_kernel<T, R, K, PD>), dim3(grid), dim3(64 * nb), lds, s, a);
     return hipGetLastError();
 }
 

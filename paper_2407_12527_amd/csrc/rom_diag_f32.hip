@@ -1,18 +1,21 @@
-// rom_diag_f32.hip -- FP32 instantiations of the row-lane sweep kernel.
+// rom_diag_f32.hip -- FP32 instantiations of the row-lane sweep kernel.  Bands of up to 8 row
+// blocks keep the field loads two blocks ahead; 16-block bands (16 wavefronts, 128 VGPRs each)
+// one block ahead.
 #include "rom_diag.h"
 
 namespace rom {
 
-hipError_t launch_diag_f32(const DiagArgs& a, int ntasks, int nb, int R, int K, hipStream_t s)
+hipError_t launch_diag_f32(const DiagArgs& a, int grid, int nb, int R, int K, hipStream_t s)
 {
+    const bool deep = nb <= 8;
     if (R == 16) {
-        if (K == 1) return launch_diag_t<float, 16, 1>(a, ntasks, nb, s);
-        if (K == 2) return launch_diag_t<float, 16, 2>(a, ntasks, nb, s);
-        if (K == 4) return launch_diag_t<float, 16, 4>(a, ntasks, nb, s);
+        if (K == 1) return deep ? launch_diag_t<float, 16, 1, 2>(a, grid, nb, s) : launch_diag_t<float, 16, 1, 1>(a, grid, nb, s);
+        if (K == 2) return launch_diag_t<float, 16, 2, 2>(a, grid, nb, s);
+        if (K == 4) return launch_diag_t<float, 16, 4, 2>(a, grid, nb, s);
     } else if (R == 64) {
-        if (K == 1) return launch_diag_t<float, 64, 1>(a, ntasks, nb, s);
-        if (K == 2) return launch_diag_t<float, 64, 2>(a, ntasks, nb, s);
-        if (K == 4) return launch_diag_t<float, 64, 4>(a, ntasks, nb, s);
+        if (K == 1) return deep ? launch_diag_t<float, 64, 1, 2>(a, grid, nb, s) : launch_diag_t<float, 64, 1, 1>(a, grid, nb, s);
+        if (K == 2) return launch_diag_t<float, 64, 2, 2>(a, grid, nb, s);
+        if (K == 4) return launch_diag_t<float, 64, 4, 2>(a, grid, nb, s);
     }
     return hipErrorInvalidValue;
 }

@@ -37,11 +37,13 @@ struct DiagArgs {
     const LaneDev* ords;       // [tasks][NO] (a, b, w of each ordinate; padding has w = 0)
     const ProblemDev* probs;
     const SystemDev* sys;
+    const int2* tickets;       // (task, band), band-major
+    int32_t ntickets;
     int32_t spin_limit;
     int32_t mode_all;
-    int32_t wrap_cols;         // columns of the LDS row buffer that carries a block's top row to
-                               // the next round of the workgroup's waves (0: one round suffices)
     int32_t pad;
+    void* edge;                // band top-row pool (T)
+    long long* prog;           // band progress counters
     const void* sigma_t;       // field pool (T)
     const void* src;           // isotropic source pool (T)
     void* part;                // partial scalar-flux pool (T)
@@ -58,7 +60,10 @@ struct CombineArgs {
     const int64_t* slot_off;
     const int2* blocks;        // (system, first cell) per block
     int32_t cells_per_block;
+    int32_t many_cpt;          // 0: one wave sums all slots of 4 cells per thread; 1, 2, 4, 8: the
+                               // many-slot combine, tiles of 64 * many_cpt cells (= cells_per_block)
     int32_t nsys;
+    int32_t pad0;
     int32_t mode;              // 0: source-iteration step, 1: plain sum (single sweep)
     int32_t max_iter;
     double tol;
@@ -101,11 +106,12 @@ bool sweep_tile_supported(int tx, int ty);
 bool sweep_tile_supported_fp64(int tx, int ty);
 size_t sweep_lds_bytes(bool fp64, int tx, int ty, bool ang, int L, int nw);
 // Row-lane sweep: R rows per lane block (16 or 64), K ordinates per lane (1, 2, 4; FP64: 1, 2),
-// nb wavefronts per workgroup (1..16), one workgroup per task.
+// nb wavefronts (row blocks) per workgroup (1..16; 1..8 when K * sizeof(T) >= 16), persistent
+// workgroups taking (task, band) tickets.
 bool diag_supported(bool fp64, int R, int K);
 int diag_max_nb(bool fp64, int K);
-size_t diag_lds_bytes(bool fp64, int R, int K, int nb, int wrap_cols);
-hipError_t launch_diag(const DiagArgs& a, int ntasks, int nb, bool fp64, int R, int K, hipStream_t s);
+size_t diag_lds_bytes(bool fp64, int R, int K, int nb);
+hipError_t launch_diag(const DiagArgs& a, int grid, int nb, bool fp64, int R, int K, hipStream_t s);
 hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s);
 hipError_t launch_sweep_prologue(Ctl* ctl, hipStream_t s);
 hipError_t launch_reset_systems(SysCtl* sc, int nsys, Ctl* ctl, hipStream_t s);

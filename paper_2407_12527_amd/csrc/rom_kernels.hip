@@ -47,6 +47,47 @@ __device__ void finalize_iteration(const CombineArgs& A)
     A.ctl->active = active;
 }
 
+// Block maxima (wave reduction, then across the 4 waves), the per-system FP64 maxima as atomics,
+// and the last block's finalize of the iteration.
+__device__ __forceinline__ void combine_tail(const CombineArgs& A, bool run, int s, double dmax, double pmax)
+{
+    const int tid = threadIdx.x;
+    for (int off = 32; off > 0; off >>= 1) {
+        dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
+        pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
+    }
+    __shared__ double sd[4], sp[4];
+    if ((tid & 63) == 0) {
+        sd[tid >> 6] = dmax;
+        sp[tid >> 6] = pmax;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        dmax = fmax(fmax(sd[0], sd[1]), fmax(sd[2], sd[3]));
+        pmax = fmax(fmax(sp[0], sp[1]), fmax(sp[2], sp[3]));
+        if (run && A.mode == 0) {
+            atomicMax(&A.sysctl[s].dmax_bits, dbits(dmax));  // non-negative doubles order as integers
+            atomicMax(&A.sysctl[s].pmax_bits, dbits(pmax));
+        }
+        // The maxima are device-scope atomics; waiting for their completion before counting the
+        // block in is all the last block needs (the fluxes themselves are read by later kernels).
+        stores_complete();
+        const int done = atomicAdd(&A.ctl->blocks_done, 1);
+        if (done == (int)gridDim.x - 1) {
+            if (A.mode == 0) finalize_iteration(A);
+            if (A.ctl->t_last > A.ctl->t_first && A.ctl->t_first != ~0ull) {
+                A.ctl->sweep_ticks += A.ctl->t_last - A.ctl->t_first;
+                A.ctl->sweeps += 1;
+            }
+            A.ctl->t_first = ~0ull;
+            A.ctl->t_last = 0ull;
+            A.ctl->blocks_done = 0;
+            A.ctl->ticket = 0;
+            A.ctl->epoch += 1;
+        }
+    }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void combine_kernel(CombineArgs A)
 {
@@ -101,41 +142,75 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs A)
             }
         }
     }
-    // block maxima: wave reduction, then across the 4 waves
-    for (int off = 32; off > 0; off >>= 1) {
-        dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
-        pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
-    }
-    __shared__ double sd[4], sp[4];
-    if ((tid & 63) == 0) {
-        sd[tid >> 6] = dmax;
-        sp[tid >> 6] = pmax;
+    combine_tail(A, run, s, dmax, pmax);
+}
+
+// Combine for systems with many partial slots (the row-lane sweep writes one per task): a block
+// owns 64 * CPT cells, its four waves sum interleaved quarters of the slot list (two independent
+// chains each, so loads stay in flight), and the per-cell total is formed in a fixed order,
+// ((w0 + w1) + (w2 + w3)), so results are deterministic.
+template <typename T, int CPT>
+__global__ __launch_bounds__(256) void combine_many_kernel(CombineArgs A)
+{
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (A.mode == 0 && A.ctl->active == 0) return;
+    const int2 blk = A.blocks[blockIdx.x];
+    const int s = blk.x;
+    const SystemDev& SD = A.sys[s];
+    const ProblemDev& P = A.probs[SD.prob];
+    const int cells = P.nx * P.ny;
+    const bool run = A.mode == 1 || A.sysctl[s].state == 0;
+    __shared__ T wsum[4][64 * CPT];
+    double dmax = 0.0, pmax = 0.0;
+    if (run) {
+        const T* __restrict__ part = (const T*)A.part;
+        const int ns = SD.nslots;
+        const int64_t* __restrict__ soff = A.slot_off;
+        const int32_t* __restrict__ sord = A.slot_order + SD.slot_first;
+        T a0[CPT], a1[CPT];
+        int cl[CPT];
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            a0[c] = a1[c] = T(0);
+            cl[c] = min(blk.y + c * 64 + lane, cells - 1);  // clamped: a valid address, result unused
+        }
+        int k = wave;
+        for (; k + 4 < ns; k += 8) {
+            const T* __restrict__ p0 = part + soff[sord[k]];
+            const T* __restrict__ p1 = part + soff[sord[k + 4]];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) {
+                a0[c] += p0[cl[c]];
+                a1[c] += p1[cl[c]];
+            }
+        }
+        if (k < ns) {
+            const T* __restrict__ p0 = part + soff[sord[k]];
+#pragma unroll
+            for (int c = 0; c < CPT; ++c) a0[c] += p0[cl[c]];
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) wsum[wave][c * 64 + lane] = a0[c] + a1[c];
     }
     __syncthreads();
-    if (tid == 0) {
-        dmax = fmax(fmax(sd[0], sd[1]), fmax(sd[2], sd[3]));
-        pmax = fmax(fmax(sp[0], sp[1]), fmax(sp[2], sp[3]));
-        if (run && A.mode == 0) {
-            atomicMax(&A.sysctl[s].dmax_bits, dbits(dmax));  // non-negative doubles order as integers
-            atomicMax(&A.sysctl[s].pmax_bits, dbits(pmax));
-        }
-        // The maxima are device-scope atomics; waiting for their completion before counting the
-        // block in is all the last block needs (the fluxes themselves are read by later kernels).
-        stores_complete();
-        const int done = atomicAdd(&A.ctl->blocks_done, 1);
-        if (done == (int)gridDim.x - 1) {
-            if (A.mode == 0) finalize_iteration(A);
-            if (A.ctl->t_last > A.ctl->t_first && A.ctl->t_first != ~0ull) {
-                A.ctl->sweep_ticks += A.ctl->t_last - A.ctl->t_first;
-                A.ctl->sweeps += 1;
+    if (run) {
+        T* __restrict__ phi = (T*)A.phi + SD.phi_off;
+        T* __restrict__ src = (T*)A.src + SD.src_off;
+        const T* __restrict__ ss = (const T*)A.sigma_s + P.field_off;
+        const T* __restrict__ q = (const T*)A.q + P.field_off;
+        for (int e = tid; e < 64 * CPT; e += 256) {
+            const int cell = blk.y + e;
+            if (cell < cells) {
+                const T v = (wsum[0][e] + wsum[1][e]) + (wsum[2][e] + wsum[3][e]);
+                const T old = phi[cell];
+                dmax = fmax(dmax, fabs((double)v - (double)old));
+                pmax = fmax(pmax, fabs((double)v));
+                phi[cell] = v;
+                src[cell] = fma(ss[cell], v, q[cell]);
             }
-            A.ctl->t_first = ~0ull;
-            A.ctl->t_last = 0ull;
-            A.ctl->blocks_done = 0;
-            A.ctl->ticket = 0;
-            A.ctl->epoch += 1;
         }
     }
+    combine_tail(A, run, s, dmax, pmax);
 }
 
 // Prepare a sweep that is not preceded by a combine step: reset the ticket counter, new epoch.
@@ -411,7 +486,11 @@ hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty,
 hipError_t launch_diag_f32(const DiagArgs&, int, int, int, int, hipStream_t);
 hipError_t launch_diag_f64(const DiagArgs&, int, int, int, int, hipStream_t);
 
-int diag_max_nb(bool fp64, int K) { return K * (fp64 ? 8 : 4) >= 16 ? 8 : kDiagMaxWaves; }
+int diag_max_nb(bool fp64, int K)
+{
+    (void)fp64;
+    return K > 1 ? 8 : kDiagMaxWaves;
+}
 
 bool diag_supported(bool fp64, int R, int K)
 {
@@ -419,22 +498,39 @@ bool diag_supported(bool fp64, int R, int K)
     return fp64 ? (K == 1 || K == 2) : (K == 1 || K == 2 || K == 4);
 }
 
-size_t diag_lds_bytes(bool fp64, int R, int K, int nb, int wrap_cols)
+size_t diag_lds_bytes(bool fp64, int R, int K, int nb)
 {
     const size_t no = (size_t)(kWave / R) * K;
     const size_t ring = R == 16 ? 64 : 128;
-    return (fp64 ? 8 : 4) * (((size_t)(nb - 1) * ring + (size_t)wrap_cols) * no + (size_t)kWave * K) +
-           sizeof(int) * 2 * kDiagMaxWaves;
+    return (fp64 ? 8 : 4) * (size_t)(nb - 1) * ring * no + sizeof(int) * (2 * kDiagMaxWaves + 1);
 }
 
-hipError_t launch_diag(const DiagArgs& a, int ntasks, int nb, bool fp64, int R, int K, hipStream_t s)
+hipError_t launch_diag(const DiagArgs& a, int grid, int nb, bool fp64, int R, int K, hipStream_t s)
 {
     if (!diag_supported(fp64, R, K)) return hipErrorInvalidValue;
-    return fp64 ? launch_diag_f64(a, ntasks, nb, R, K, s) : launch_diag_f32(a, ntasks, nb, R, K, s);
+    return fp64 ? launch_diag_f64(a, grid, nb, R, K, s) : launch_diag_f32(a, grid, nb, R, K, s);
 }
 
 hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s)
 {
+    if (a.many_cpt > 0) {
+        // block tiles of 64 * many_cpt cells (cells_per_block must match)
+        if (a.cells_per_block != 64 * a.many_cpt) return hipErrorInvalidValue;
+        if (fp64) {
+            if (a.many_cpt == 1) hipLaunchKernelGGL((combine_many_kernel<double, 1>), dim3(nblocks), dim3(256), 0, s, a);
+            else if (a.many_cpt == 2) hipLaunchKernelGGL((combine_many_kernel<double, 2>), dim3(nblocks), dim3(256), 0, s, a);
+            else if (a.many_cpt == 4) hipLaunchKernelGGL((combine_many_kernel<double, 4>), dim3(nblocks), dim3(256), 0, s, a);
+            else if (a.many_cpt == 8) hipLaunchKernelGGL((combine_many_kernel<double, 8>), dim3(nblocks), dim3(256), 0, s, a);
+            else return hipErrorInvalidValue;
+        } else {
+            if (a.many_cpt == 1) hipLaunchKernelGGL((combine_many_kernel<float, 1>), dim3(nblocks), dim3(256), 0, s, a);
+            else if (a.many_cpt == 2) hipLaunchKernelGGL((combine_many_kernel<float, 2>), dim3(nblocks), dim3(256), 0, s, a);
+            else if (a.many_cpt == 4) hipLaunchKernelGGL((combine_many_kernel<float, 4>), dim3(nblocks), dim3(256), 0, s, a);
+            else if (a.many_cpt == 8) hipLaunchKernelGGL((combine_many_kernel<float, 8>), dim3(nblocks), dim3(256), 0, s, a);
+            else return hipErrorInvalidValue;
+        }
+        return hipGetLastError();
+    }
     if (fp64)
         hipLaunchKernelGGL(combine_kernel<double>, dim3(nblocks), dim3(256), 0, s, a);
     else
