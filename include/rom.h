@@ -126,8 +126,9 @@ typedef struct {
     double final_r;        /* last relative change (largest over systems) */
     int64_t updates;       /* cell x ordinate upwind updates performed */
     double device_ms;      /* device time of the solve, from events on the handle's stream */
-    double sweep_ms;       /* summed duration of the sweep launches that did work, first wave
-                              start to last wave end, from the device real-time clock */
+    double sweep_ms;       /* summed duration of the sweep launches that did work, from the end of
+                              the kernel before each (its dispatch) to its last wave's end, on the
+                              device real-time clock */
     int32_t sweeps;        /* sweep launches that did work */
     int32_t tile_x, tile_y;/* strip sweep: chunk x strip shape; row-lane sweep: ordinates per lane
                               and rows per lane block (set or autotuned) */

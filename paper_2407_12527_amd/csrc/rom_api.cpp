@@ -1042,6 +1042,7 @@ void enqueue_iteration(Plan& P, hipStream_t s, double tol)
             c.sysctl = P.d_sysctl.as<SysCtl>();
             HIPCHK(launch_contract(c, P.fp64 ? 2 : 0, s));
         }
+        HIPCHK(launch_mark(P.d_ctl.as<Ctl>(), s));  // the sweep is timed from here, not from the combine
     }
     HIPCHK(P.launch_sweep_any(0, s));
     const CombineArgs ca = P.combine_args(0, tol);
@@ -1104,6 +1105,7 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
         }
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
+            HIPCHK(launch_mark(P.d_ctl.as<Ctl>(), s));
             for (int k = 0; k < K; ++k) enqueue_iteration(P, s, tol);
         } catch (...) {
             hipGraph_t g;

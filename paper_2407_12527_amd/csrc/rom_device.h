@@ -107,6 +107,8 @@ struct Ctl {
     unsigned long long t_first;     // real-time clock at the first wave start of the running sweep
     unsigned long long t_last;      // ... and at the last wave end
     unsigned long long sweep_ticks; // summed sweep durations (real-time clock ticks)
+    unsigned long long t_mark;      // end of the kernel that precedes the next sweep: a sweep lasts
+                                    // from here (its dispatch, as a profiler sees it) to its last wave
 };
 
 }  // namespace rom

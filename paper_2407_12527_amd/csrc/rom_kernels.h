@@ -114,6 +114,7 @@ size_t diag_lds_bytes(bool fp64, int R, int K, int nb);
 hipError_t launch_diag(const DiagArgs& a, int grid, int nb, bool fp64, int R, int K, hipStream_t s);
 hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s);
 hipError_t launch_sweep_prologue(Ctl* ctl, hipStream_t s);
+hipError_t launch_mark(Ctl* ctl, hipStream_t s);
 hipError_t launch_reset_systems(SysCtl* sc, int nsys, Ctl* ctl, hipStream_t s);
 hipError_t launch_fill(void* p, int64_t n, bool fp64, double v, hipStream_t s);
 hipError_t launch_moments(const MomentsArgs& a, bool fp64, hipStream_t s);

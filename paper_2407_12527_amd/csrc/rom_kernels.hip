@@ -76,11 +76,13 @@ __device__ __forceinline__ void combine_tail(const CombineArgs& A, bool run, int
         if (done == (int)gridDim.x - 1) {
             if (A.mode == 0) finalize_iteration(A);
             if (A.ctl->t_last > A.ctl->t_first && A.ctl->t_first != ~0ull) {
-                A.ctl->sweep_ticks += A.ctl->t_last - A.ctl->t_first;
+                const unsigned long long t0 = A.ctl->t_mark < A.ctl->t_first ? A.ctl->t_mark : A.ctl->t_first;
+                A.ctl->sweep_ticks += A.ctl->t_last - t0;
                 A.ctl->sweeps += 1;
             }
             A.ctl->t_first = ~0ull;
             A.ctl->t_last = 0ull;
+            A.ctl->t_mark = wall_clock64();  // this kernel ends here; the next sweep follows
             A.ctl->blocks_done = 0;
             A.ctl->ticket = 0;
             A.ctl->epoch += 1;
@@ -213,6 +215,18 @@ __global__ __launch_bounds__(256) void combine_many_kernel(CombineArgs A)
     combine_tail(A, run, s, dmax, pmax);
 }
 
+// Mark the start of a captured run of iterations (its first sweep is timed from here).
+__global__ void mark_kernel(Ctl* ctl)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) ctl->t_mark = wall_clock64();
+}
+
+hipError_t launch_mark(Ctl* ctl, hipStream_t s)
+{
+    hipLaunchKernelGGL(mark_kernel, dim3(1), dim3(64), 0, s, ctl);
+    return hipGetLastError();
+}
+
 // Prepare a sweep that is not preceded by a combine step: reset the ticket counter, new epoch.
 __global__ void sweep_prologue_kernel(Ctl* ctl)
 {
@@ -243,6 +257,7 @@ __global__ void reset_systems_kernel(SysCtl* sc, int nsys, Ctl* ctl)
         ctl->t_first = ~0ull;
         ctl->t_last = 0ull;
         ctl->sweep_ticks = 0ull;
+        ctl->t_mark = wall_clock64();
         ctl->ticket = 0;
         ctl->blocks_done = 0;
         ctl->epoch += 1;
