@@ -56,6 +56,10 @@ extern "C" {
 #define ROM_SCAT_LINEAR 1 /* P = 1 + g cos(xi) (eq. (2.1)) */
 #define ROM_SCAT_HG 2     /* Henyey-Greenstein (1-g^2)/(1+g^2-2g cos xi)^{3/2} */
 #define ROM_SCAT_DENSE 3  /* caller's P[l'][l] */
+/* Flag OR-ed into the kind of rom_set_scattering: rescale each incoming ordinate's row of P so
+ * that sum_l w_l P_l'l = 1 for every l' (mass conservation at the discrete level, the
+ * normalisation the remark of Sec. 3.1 proposes).  Without it W = w P is used as it is. */
+#define ROM_SCAT_NORMALIZE 0x10
 
 #define ROM_ORD_STRATIFIED 0 /* ROM: one uniform draw per (zeta,theta) cell, mirrored (Sec. 3.1) */
 #define ROM_ORD_IID_SPHERE 1 /* n i.i.d. uniform directions on the sphere */
@@ -176,9 +180,14 @@ int rom_set_ordinates(rom_handle* h, int32_t n, const double* dirs, const double
  * restores it.  Requires ordinates to be set; cleared when they change. */
 int rom_set_inflow_angular(rom_handle* h, int32_t face, const double* vals);
 
-/* Scattering kernel P_l'l = P(u_l', u_l), weights W = w_l' P_l'l, self term included and not
- * renormalised (eq. (3.4)).  LINEAR and HG are folded over +-zeta' (X-Y solutions are even in
- * zeta).  DENSE takes P [n][n] (caller's order) and requires ordinates to be set. */
+/* Scattering kernel P_l'l = P(u_l', u_l), weights W = w_l' P_l'l, self term included (eq. (3.4)),
+ * not renormalised unless kind carries ROM_SCAT_NORMALIZE (then P_l'l / r_l' with
+ * r_l' = sum_l w_l P_l'l).  LINEAR and HG are folded over +-zeta' (X-Y solutions are even in
+ * zeta).  The folded LINEAR kernel is 1 + g (c c' + s s') (eq. (2.1)), of rank 3, so its source
+ * is sigma_s (phi~ + g (c Jx~ + s Jy~)) + q from three moments of the previous iterate
+ * (phi~, Jx~, Jy~ = sums of w psi / r, w c psi / r, w s psi / r), formed inside the sweep: O(n)
+ * work per cell, no angular flux stored.  HG and DENSE use the dense contraction.  DENSE takes
+ * P [n][n] (caller's order) and requires ordinates to be set. */
 int rom_set_scattering(rom_handle* h, int32_t kind, double g, const double* P);
 
 /* ---- compute ------------------------------------------------------------------------------ */

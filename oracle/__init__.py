@@ -22,6 +22,7 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 
 SCHEME_STEP, SCHEME_DD = 0, 1
 SCAT_ISO, SCAT_LINEAR, SCAT_HG, SCAT_DENSE = 0, 1, 2, 3
+SCAT_NORMALIZE = 0x10  # flag OR-ed into a kernel kind: rows of P rescaled to unit weighted sum
 ORD_STRATIFIED, ORD_IID_SPHERE, ORD_UNIFORM2D, ORD_GAUSS2D = 0, 1, 2, 3
 OK, NOT_CONVERGED = 0, 1
 
@@ -160,7 +161,8 @@ def gauss_legendre(n: int):
 
 
 def build_W(dirs, w, kind=SCAT_ISO, g=0.0, fold=1, P=None) -> np.ndarray:
-    """W[l', l] = w_l' P(u_l', u_l) (eq. (3.4))."""
+    """W[l', l] = w_l' P(u_l', u_l) (eq. (3.4)); with kind | SCAT_NORMALIZE each row l' of P is
+    divided by r_l' = sum_l w_l P(u_l', u_l) (the remark of Sec. 3.1 on mass conservation)."""
     dirs = _f64(dirs)
     w = _f64(w)
     n = w.shape[0]

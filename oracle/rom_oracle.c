@@ -45,6 +45,7 @@
 #define ORC_SCAT_LINEAR 1
 #define ORC_SCAT_HG 2
 #define ORC_SCAT_DENSE 3
+#define ORC_SCAT_NORMALIZE 0x10 /* flag: rescale P so that sum_l w_l P_l'l = 1 (remark, Sec. 3.1) */
 
 #define ORC_ORD_STRATIFIED 0
 #define ORC_ORD_IID_SPHERE 1
@@ -286,7 +287,8 @@ int orc_quadrature_gauss2d(int N, double *dirs, double *w)
 }
 
 /* ------------------------------------------------------------------------------------------ */
-/* Scattering: W[l'][l] = w_l' * P(u_l', u_l), eq. (3.4), self term included, not renormalized. */
+/* Scattering: W[l'][l] = w_l' * P(u_l', u_l), eq. (3.4), self term included; optionally with */
+/* each row of P renormalized (the remark of Sec. 3.1).                                        */
 /* ------------------------------------------------------------------------------------------ */
 
 /* Phase functions of the cosine mu between two 3-D directions.  LINEAR is the kernel
@@ -315,24 +317,40 @@ static double phase(int kind, double g, double mu)
 int orc_build_W(int n, const double *dirs, const double *w, int kind, double g, int fold,
                 const double *P, double *W)
 {
+    const int normalize = (kind & ORC_SCAT_NORMALIZE) != 0;
+    kind &= ~ORC_SCAT_NORMALIZE;
     if (n <= 0 || !dirs || !w || !W) return ORC_EARG;
     if (kind == ORC_SCAT_DENSE && !P) return ORC_EARG;
+    double *row = (double *)malloc(sizeof(double) * n);
+    if (!row) return ORC_ENOMEM;
     for (int lp = 0; lp < n; ++lp) {
         for (int l = 0; l < n; ++l) {
-            double pv;
             if (kind == ORC_SCAT_DENSE) {
-                pv = P[(size_t)lp * n + l];
+                row[l] = P[(size_t)lp * n + l];
             } else {
                 double cc = dirs[3 * lp] * dirs[3 * l] + dirs[3 * lp + 1] * dirs[3 * l + 1];
                 double zz = dirs[3 * lp + 2] * dirs[3 * l + 2];
                 if (fold)
-                    pv = 0.5 * (phase(kind, g, cc + zz) + phase(kind, g, cc - zz));
+                    row[l] = 0.5 * (phase(kind, g, cc + zz) + phase(kind, g, cc - zz));
                 else
-                    pv = phase(kind, g, cc + zz);
+                    row[l] = phase(kind, g, cc + zz);
             }
-            W[(size_t)lp * n + l] = w[lp] * pv;
         }
+        /* Normalized: the remark after eq. (3.5) asks that everything scattered out of the
+         * incoming direction l' arrives somewhere, sum over outgoing l of w_l P_l'l = 1; the
+         * row l' of P is divided by that sum r_l'. */
+        double r = 1.0;
+        if (normalize) {
+            r = 0.0;
+            for (int l = 0; l < n; ++l) r += w[l] * row[l];
+            if (!(r > 0.0)) {
+                free(row);
+                return ORC_EARG;
+            }
+        }
+        for (int l = 0; l < n; ++l) W[(size_t)lp * n + l] = w[lp] * (row[l] / r);
     }
+    free(row);
     return ORC_OK;
 }
 
@@ -541,9 +559,9 @@ int orc_ensemble(const orc_grid *g, const double *sigma_t, const double *sigma_s
     const size_t cells = (size_t)g->nx * g->ny;
     double *dirs = (double *)malloc(sizeof(double) * 3 * n);
     double *w = (double *)malloc(sizeof(double) * n);
-    double *W = scat_kind == ORC_SCAT_ISO ? NULL : (double *)malloc(sizeof(double) * (size_t)n * n);
+    double *W = (scat_kind & ~ORC_SCAT_NORMALIZE) == ORC_SCAT_ISO ? NULL : (double *)malloc(sizeof(double) * (size_t)n * n);
     double *all = phis ? phis : (double *)malloc(sizeof(double) * cells * (size_t)t);
-    if (!dirs || !w || !all || (scat_kind != ORC_SCAT_ISO && !W)) {
+    if (!dirs || !w || !all || ((scat_kind & ~ORC_SCAT_NORMALIZE) != ORC_SCAT_ISO && !W)) {
         free(dirs);
         free(w);
         free(W);

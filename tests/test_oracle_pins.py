@@ -214,6 +214,108 @@ def test_hg_fold_column_sums_near_one(orc):
     assert Wr.sum(0).max() > 1.3  # the unfolded upper-hemisphere kernel over-counts forward peaks
 
 
+def test_linear_kernel_is_rank_three(orc):
+    """The folded linear kernel on any set is w_l' (1 + g(c c' + s s')): W = w (1 1^T + g c c^T +
+    g s s^T), rank 3, so the contraction sum_l' W[l', l] psi_l' equals
+    phi + g (c_l Jx + s_l Jy) with phi, Jx, Jy the w-, w c- and w s-moments of psi (eq. (2.1),
+    eq. (3.4)).  Checked against numpy's matrix rank and a random psi."""
+    d, w = orc.generate(orc.ORD_IID_SPHERE, 40, seed=5)
+    g = 0.9
+    W = orc.build_W(d, w, orc.SCAT_LINEAR, g, fold=1)
+    assert np.linalg.matrix_rank(W, tol=1e-10) == 3
+    psi = np.random.default_rng(1).uniform(0, 1, len(w))
+    phi, jx, jy = w @ psi, (w * d[:, 0]) @ psi, (w * d[:, 1]) @ psi
+    np.testing.assert_allclose(W.T @ psi, phi + g * (d[:, 0] * jx + d[:, 1] * jy), rtol=1e-14)
+
+
+@pytest.mark.parametrize("kind,g", [("hg", 0.8), ("hg", 0.95), ("linear", 0.9)])
+def test_normalized_kernel_spectral_radius(orc, kind, g):
+    """Normalizing each row of P to a unit weighted sum (remark of Sec. 3.1) makes W^T a
+    contraction in the w-weighted l1 norm, so rho(W) <= 1 for every nonnegative kernel; the raw
+    HG kernel on a small random set exceeds 1 (the source of divergent samples).  A column
+    rescaling instead of a row rescaling fails the weighted-sum identity checked here."""
+    k = orc.SCAT_HG if kind == "hg" else orc.SCAT_LINEAR
+    worst_raw = 0.0
+    for seed in range(6):
+        d, w = orc.generate(orc.ORD_IID_SPHERE, 16, seed=seed)
+        Wn = orc.build_W(d, w, k | orc.SCAT_NORMALIZE, g, fold=1)
+        assert np.all(Wn >= 0.0)
+        rho = max(abs(np.linalg.eigvals(Wn)))
+        assert rho <= 1.0 + 1e-12
+        # sum over outgoing l of w_l P~_l'l = 1, i.e. sum_l w_l W~[l', l] = w_l'
+        np.testing.assert_allclose(Wn @ w, w, rtol=1e-13)
+        worst_raw = max(worst_raw, max(abs(np.linalg.eigvals(orc.build_W(d, w, k, g, fold=1)))))
+    if kind == "hg":
+        assert worst_raw > 1.5
+
+
+def test_normalization_is_identity_where_rows_already_sum_to_one(orc):
+    """ISO rows sum to sum w = 1, and the folded linear kernel's rows sum to
+    1 + g (c' sum w c + s' sum w s) = 1 on mirror-symmetric sets (eq. (3.5)): normalizing changes
+    nothing there.  On an i.i.d. set the linear rows differ from 1 and the change is visible."""
+    for kind, p1, p2 in ((orc.ORD_STRATIFIED, 2, 3), (orc.ORD_UNIFORM2D, 4, 0), (orc.ORD_GAUSS2D, 5, 0)):
+        d, w = orc.generate(kind, p1, p2, seed=2)
+        for sk, g in ((orc.SCAT_ISO, 0.0), (orc.SCAT_LINEAR, 0.9)):
+            np.testing.assert_allclose(orc.build_W(d, w, sk | orc.SCAT_NORMALIZE, g), orc.build_W(d, w, sk, g),
+                                       rtol=1e-13, atol=1e-16)
+    d, w = orc.generate(orc.ORD_IID_SPHERE, 12, seed=2)
+    diff = orc.build_W(d, w, orc.SCAT_LINEAR | orc.SCAT_NORMALIZE, 0.9) - orc.build_W(d, w, orc.SCAT_LINEAR, 0.9)
+    assert np.max(np.abs(diff)) > 1e-3
+
+
+def test_normalized_kernel_conserves_particles(orc):
+    """C-4 summed over ordinates with weights w: with normalized rows the scattering gain
+    integrates to exactly sigma_s phi^{k-1} per cell (sum_l w_l W~[l', l] = w_l'), so
+    sum_l w_l [|c| dy sum(psi_out - psi_in)_x + |s| dx sum(psi_out - psi_in)_y]
+    + sum sigma_t phi^k dA = sum (sigma_s phi^{k-1} + q) dA at every iterate.  The raw HG kernel
+    on the same i.i.d. set breaks it, which shows the identity has teeth."""
+    rng = np.random.default_rng(11)
+    nx, ny = 7, 5
+    box = (0.0, 1.0, 0.0, 1.3)
+    dx, dy = 1.0 / nx, 1.3 / ny
+    st, ss, q = _rand_fields(rng, nx, ny, 0.5)
+    inflow = {"left": rng.uniform(0, 1, ny), "bottom": rng.uniform(0, 1, nx), "right": rng.uniform(0, 1, ny),
+              "top": rng.uniform(0, 1, nx)}
+    prob = _prob(orc, nx, ny, st, ss, q, box=box, inflow=inflow)
+    dirs, w = orc.generate(orc.ORD_IID_SPHERE, 10, seed=9)
+
+    def imbalance(W, k):
+        prev = orc.source_iterate(prob, dirs, w, W, tol=0.0, max_iter=k - 1)["phi"] if k > 1 else np.zeros(nx * ny)
+        cur = orc.source_iterate(prob, dirs, w, W, tol=0.0, max_iter=k, want_psi=True)
+        lhs = np.sum(st * cur["phi"]) * dx * dy
+        for l in range(len(w)):
+            c, s = dirs[l, 0], dirs[l, 1]
+            P = cur["psi"][l].reshape(ny, nx)
+            xin, xout = (inflow["left"], P[:, -1]) if c >= 0 else (inflow["right"], P[:, 0])
+            yin, yout = (inflow["bottom"], P[-1, :]) if s >= 0 else (inflow["top"], P[0, :])
+            lhs += w[l] * (abs(c) * dy * np.sum(xout - xin) + abs(s) * dx * np.sum(yout - yin))
+        rhs = np.sum(ss * prev + q) * dx * dy
+        return abs(lhs - rhs) / abs(rhs)
+
+    Wn = orc.build_W(dirs, w, orc.SCAT_HG | orc.SCAT_NORMALIZE, 0.8, fold=1)
+    for k in (1, 2, 4):
+        assert imbalance(Wn, k) <= 1e-12
+    assert imbalance(orc.build_W(dirs, w, orc.SCAT_HG, 0.8, fold=1), 3) > 1e-3
+
+
+def test_infinite_medium_normalized_kernel(orc):
+    """C-2 with a normalized HG kernel on an i.i.d. set: the constant fixed point
+    v = (sigma_t I - sigma_s W~^T)^{-1} q 1 is reproduced, and the iteration converges although
+    the raw kernel's sigma_s rho(W) exceeds sigma_t on this set."""
+    nx, ny = 5, 4
+    st, ss, qv = 1.0, 0.8, 1.0
+    dirs, w = orc.generate(orc.ORD_IID_SPHERE, 16, seed=0)
+    n = len(w)
+    W = orc.build_W(dirs, w, orc.SCAT_HG | orc.SCAT_NORMALIZE, 0.8, fold=1)
+    assert ss * max(abs(np.linalg.eigvals(orc.build_W(dirs, w, orc.SCAT_HG, 0.8, fold=1)))) > st
+    v = np.linalg.solve(st * np.eye(n) - ss * W.T, np.full(n, qv))
+    ang = {k: np.repeat(v[:, None], ny if k in ("left", "right") else nx, 1) for k in ("left", "right", "bottom", "top")}
+    prob = _prob(orc, nx, ny, np.full(nx * ny, st), np.full(nx * ny, ss), np.full(nx * ny, qv), inflow_angular=ang)
+    res = orc.source_iterate(prob, dirs, w, W, tol=1e-15, max_iter=3000, want_psi=True)
+    assert res["status"] == 0
+    np.testing.assert_allclose(res["psi"], np.repeat(v[:, None], nx * ny, 1), rtol=1e-11)
+
+
 # ------------------------------------------------------------------------------------ sweeps
 def _lattice_path(nx, ny, alpha, beta, L, B):
     """Closed form of psi_ij = alpha psi_{i-1,j} + beta psi_{i,j-1} with psi_{-1,j} = L_j,
