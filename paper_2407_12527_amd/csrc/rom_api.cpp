@@ -117,7 +117,8 @@ struct rom_handle {
     std::vector<double> dirs, w;
     std::vector<double> ang[4];
     // scattering
-    int scat = ROM_SCAT_ISO;
+    int scat = ROM_SCAT_ISO;    // kernel kind without flags
+    bool scat_norm = false;     // ROM_SCAT_NORMALIZE: rows of P rescaled to unit weighted sum
     double g = 0.0;
     std::vector<double> Pdense;
     // execution
@@ -175,6 +176,9 @@ struct SysInput {
 
 struct Plan {
     bool fp64 = false, dd = false, aniso = false;
+    int nmom = 1;       // 4: linear-kernel moment sweep (three source planes, four partial planes)
+    int mom_r = 0;      // linear kernel normalized somewhere in the batch: form phi~ separately
+    int64_t src_len = 0;  // elements of the source pool (without its padding)
     int tx = 16, ty = 16;
     int band = 1;   // strips per sweep workgroup
     int L = 64;     // lanes per ordinate group
@@ -257,7 +261,7 @@ struct Plan {
     hipError_t launch_sweep_any(int mode_all, hipStream_t s) const
     {
         if (kind == ROM_SWEEP_DIAG) return launch_diag(diag_args(mode_all), grid, dNB, fp64, dR, dK, s);
-        return launch_sweep(sweep_args(mode_all, 0), grid, fp64, tx, ty, dd, aniso, aniso ? (fp64 ? 1 : 2) : 0, L, s);
+        return launch_sweep(sweep_args(mode_all, 0), grid, fp64, tx, ty, dd, aniso, aniso ? (fp64 ? 1 : 2) : 0, L, nmom, s);
     }
 
     SweepArgs sweep_args(int mode_all, int psi_mode) const
@@ -284,6 +288,7 @@ struct Plan {
         a.prog = d_prog.as<long long>();
         a.ctl = d_ctl.as<Ctl>();
         a.sysctl = d_sysctl.as<SysCtl>();
+        a.mom_r = mom_r;
         (void)psi_mode;
         return a;
     }
@@ -299,6 +304,8 @@ struct Plan {
         c.cells_per_block = cells_per_block;
         c.many_cpt = many_cpt;
         c.nsys = nsys;
+        c.nmom = nmom;
+        c.mom_r = mom_r;
         c.mode = mode;
         c.max_iter = max_iter;
         c.tol = tol;
@@ -469,17 +476,79 @@ std::vector<double> inflow_table(const Plan& P, const std::vector<SysInput>& in)
     return inf;
 }
 
-void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, bool aniso, int max_iter,
+// Scattering mode of a handle: 0 isotropic (source from phi), 1 linear kernel (rank-3 moment
+// contraction inside the sweep), 2 dense contraction (HG or the caller's P).
+int scat_mode(const rom_handle* h)
+{
+    if (h->scat == ROM_SCAT_ISO) return 0;
+    if (h->scat == ROM_SCAT_LINEAR) return 1;
+    return 2;
+}
+
+// Plan-structure key of a handle's scattering: the mode and whether a linear kernel is normalized.
+int scat_sig(const rom_handle* h) { return scat_mode(h) + ((scat_mode(h) == 1 && h->scat_norm) ? 8 : 0); }
+
+// 1 / r for every caller ordinate of a normalized linear-kernel system: the folded kernel
+// 1 + g (c c' + s s') of eq. (2.1) has the weighted row sums
+// r_l' = sum_l w_l (1 + g (c_l' c_l + s_l' s_l)) = sum w + g (c_l' sum w c + s_l' sum w s).
+// Empty when the kernel is not normalized (r = 1).
+std::vector<double> linear_inv_r(const rom_handle* h, const SysInput& si)
+{
+    std::vector<double> ir;
+    if (h->scat != ROM_SCAT_LINEAR || !h->scat_norm) return ir;
+    double sw = 0.0, swc = 0.0, sws = 0.0;
+    for (int l = 0; l < si.n; ++l) {
+        sw += si.w[l];
+        swc += si.w[l] * si.dirs[3 * l];
+        sws += si.w[l] * si.dirs[3 * l + 1];
+    }
+    ir.resize(si.n);
+    for (int l = 0; l < si.n; ++l) {
+        const double r = sw + h->g * (si.dirs[3 * l] * swc + si.dirs[3 * l + 1] * sws);
+        if (!(r > 0.0)) throw Fail{ROM_E_DOMAIN, "normalized linear kernel: a row sum is not positive"};
+        ir[l] = 1.0 / r;
+    }
+    return ir;
+}
+
+// Lane-table entry of caller ordinate u of system si (u < 0: a padding lane, all zero).
+void fill_lane(LaneDev& ld, const rom_handle* h, const SysInput& si, int u, const std::vector<double>& inv_r)
+{
+    const int32_t ord = ld.ord;
+    ld = LaneDev{};
+    ld.ord = ord;
+    if (u < 0) return;
+    const double c = si.dirs[3 * u], sn = si.dirs[3 * u + 1];
+    ld.a = std::fabs(c) / h->dx;
+    ld.b = std::fabs(sn) / h->dy;
+    ld.w = si.w[u];
+    ld.c = c;
+    ld.s = sn;
+    const double ir = inv_r.empty() ? 1.0 : inv_r[u];
+    ld.m1 = c * ir;
+    ld.m2 = sn * ir;
+    ld.m3 = ir;
+}
+
+// smode: scattering mode of every system of the batch (scat_mode); 2 also for a per-ordinate
+// source of a single sweep.
+void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, int smode, int max_iter,
                 bool psi_out = false)
 {
+    const bool aniso = smode == 2;
     P.fp64 = o.precision == ROM_PREC_FP64;
     P.dd = o.scheme == ROM_SCHEME_DD;
     P.aniso = aniso;
+    P.nmom = smode == 1 ? 4 : 1;
+    P.mom_r = 0;
+    if (smode == 1)
+        for (auto& si : in)
+            if (si.h->scat_norm) P.mom_r = 1;
     P.esz = P.fp64 ? 8 : 4;
     P.max_iter = max_iter;
     P.kind = o.sweep == ROM_SWEEP_DIAG ? ROM_SWEEP_DIAG : ROM_SWEEP_STRIP;
     if (P.kind == ROM_SWEEP_DIAG) {
-        if (aniso || psi_out || P.dd)
+        if (aniso || psi_out || P.dd || P.nmom != 1)
             throw Fail{ROM_E_UNSUPPORTED, "the row-lane sweep takes isotropic sources, the step scheme and no angular-flux output"};
         P.dR = o.diag_rows > 0 ? o.diag_rows : 16;
         P.dK = o.diag_k > 0 ? o.diag_k : 1;
@@ -571,8 +640,8 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         for (auto& si : in) maxstrips = std::max(maxstrips, (si.h->grid.ny + TY - 1) / TY);
         P.band = o.band > 0 ? o.band : std::min(kMaxBand, maxstrips);
         // keep the workgroup's LDS within 64 KiB when choosing automatically (two workgroups per CU)
-        while (o.band == 0 && P.band > 1 && sweep_lds_bytes(P.fp64, TX, TY, aniso, P.L, P.band) > 64 * 1024) --P.band;
-        if (sweep_lds_bytes(P.fp64, TX, TY, aniso, P.L, P.band) > 160 * 1024)
+        while (o.band == 0 && P.band > 1 && sweep_lds_bytes(P.fp64, TX, TY, aniso, P.L, P.band, P.nmom) > 64 * 1024) --P.band;
+        if (sweep_lds_bytes(P.fp64, TX, TY, aniso, P.L, P.band, P.nmom) > 160 * 1024)
             throw Fail{ROM_E_ARG, "band too large for this tile shape (LDS)"};
     }
 
@@ -589,7 +658,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         int count;             // real ordinates in the group
     };
     std::vector<std::vector<Group>> groups_pq(nprob * 4);
-    int64_t phi_sum = 0, ang_sum = 0;
+    int64_t phi_sum = 0, ang_sum = 0, src_sum = 0;
     for (int s = 0; s < P.nsys; ++s) {
         const int p = pidx[in[s].h];
         const int L = Lp[p];
@@ -609,9 +678,11 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         sd.prob = p;
         sd.npad = al;
         sd.phi_off = phi_sum;
-        sd.src_off = phi_sum;
+        sd.src_off = src_sum;
         sd.ang_off = ang_sum;
+        sd.g = scat_mode(in[s].h) == 1 ? in[s].h->g : 0.0;
         phi_sum += in[s].h->cells;
+        src_sum += in[s].h->cells * (P.nmom == 4 ? 3 : 1);
         if (aniso) ang_sum += in[s].h->cells * (int64_t)al;
         P.sys_n[s] = in[s].n;
         P.sys_w[s] = in[s].w;
@@ -671,11 +742,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
                         ld.ord = (int)uo.size();
                         const int u = b0 + k < list.size() ? list[b0 + k] : -1;
                         uo.push_back(u);
-                        if (u >= 0) {
-                            ld.a = std::fabs(in[sy].dirs[3 * u]) / h->dx;
-                            ld.b = std::fabs(in[sy].dirs[3 * u + 1]) / h->dy;
-                            ld.w = in[sy].w[u];
-                        }
+                        fill_lane(ld, h, in[sy], u, {});
                         P.lanes.push_back(ld);
                     }
                     P.slot_off.push_back(part_sum);
@@ -688,6 +755,8 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
             P.npad_al[sy] = P.sys[sy].npad = (int)uo.size();
         }
     }
+    std::vector<std::vector<double>> inv_r(P.nsys);
+    for (int s = 0; s < P.nsys; ++s) inv_r[s] = linear_inv_r(in[s].h, in[s]);
     for (int p = 0; p < nprob && P.kind == ROM_SWEEP_STRIP; ++p) {
         rom_handle* h = P.handles[p];
         const int L = Lp[p], G = 64 / L;
@@ -730,19 +799,14 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
                         W.sys[k] = gr.sys;
                         W.slot[k] = P.nslots;
                         P.slot_off.push_back(part_sum);
-                        part_sum += h->cells;
+                        part_sum += h->cells * P.nmom;  // one partial plane per moment
                         sys_slots[gr.sys].push_back(P.nslots);
                         ++P.nslots;
                         const SysInput& si = in[gr.sys];
                         for (int l = 0; l < L; ++l) {
                             LaneDev ld{};
                             ld.ord = gr.first + l;
-                            const int u = P.user_of[gr.sys][gr.first + l];
-                            if (u >= 0) {
-                                ld.a = std::fabs(si.dirs[3 * u]) / h->dx;
-                                ld.b = std::fabs(si.dirs[3 * u + 1]) / h->dy;
-                                ld.w = si.w[u];
-                            }
+                            fill_lane(ld, h, si, P.user_of[gr.sys][gr.first + l], inv_r[gr.sys]);
                             P.lanes.push_back(ld);
                         }
                     } else {
@@ -797,7 +861,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         for (auto& si : in) tot += si.h->cells;
         for (auto& sd : P.sys) maxslots = std::max(maxslots, sd.nslots);
         P.many_cpt = 0;
-        if (maxslots > 8) {
+        if (maxslots > 8 && P.nmom == 1) {
             P.many_cpt = 1;
             while (P.many_cpt < 8 && tot / (64 * 2 * P.many_cpt) > 4 * device_cus()) P.many_cpt *= 2;
             P.cells_per_block = 64 * P.many_cpt;
@@ -853,8 +917,9 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         HIPCHK(P.d_inflow.alloc(256));
     }
 
-    HIPCHK(P.d_src.alloc((phi_sum + 2 * kPoolPad) * P.esz));
-    HIPCHK(hipMemset(P.d_src.p, 0, (phi_sum + 2 * kPoolPad) * P.esz));
+    P.src_len = src_sum;
+    HIPCHK(P.d_src.alloc((src_sum + 2 * kPoolPad) * P.esz));
+    HIPCHK(hipMemset(P.d_src.p, 0, (src_sum + 2 * kPoolPad) * P.esz));
     HIPCHK(P.d_phi.alloc(phi_sum * P.esz));
     HIPCHK(P.d_part.alloc(std::max<int64_t>(part_sum, 1) * P.esz));
     HIPCHK(P.d_edge.alloc(std::max<int64_t>(edge_sum, 1) * P.esz));
@@ -889,15 +954,27 @@ void build_kernel_matrices(Plan& P, const std::vector<SysInput>& in, hipStream_t
         const int al = P.npad_al[s];
         const auto& uo = P.user_of[s];
         const int npad = (int)uo.size();
+        auto kernel = [&](int uk, int un) {  // P(u_uk incoming, u_un outgoing)
+            if (h->scat == ROM_SCAT_DENSE) return h->Pdense[(size_t)uk * h->n + un];
+            return phase_folded(h->scat, h->g, in[s].dirs + 3 * uk, in[s].dirs + 3 * un);
+        };
+        // normalized kernel: row uk divided by r_uk = sum over outgoing un of w_un P(uk, un)
+        std::vector<double> inv_r(in[s].n, 1.0);
+        if (h->scat_norm) {
+            for (int uk = 0; uk < in[s].n; ++uk) {
+                double r = 0.0;
+                for (int un = 0; un < in[s].n; ++un) r += in[s].w[un] * kernel(uk, un);
+                if (!(r > 0.0)) throw Fail{ROM_E_DOMAIN, "normalized kernel: a row sum is not positive"};
+                inv_r[uk] = 1.0 / r;
+            }
+        }
         for (int nn = 0; nn < npad; ++nn) {
             const int un = uo[nn];
             if (un < 0) continue;
             for (int kk = 0; kk < npad; ++kk) {
                 const int uk = uo[kk];
                 if (uk < 0) continue;
-                double pv;
-                if (h->scat == ROM_SCAT_DENSE) pv = h->Pdense[(size_t)uk * h->n + un];
-                else pv = phase_folded(h->scat, h->g, in[s].dirs + 3 * uk, in[s].dirs + 3 * un);
+                const double pv = kernel(uk, un) * inv_r[uk];
                 const int64_t idx = P.pt_off[s] + (int64_t)nn * al + kk;
                 if (P.fp64) bt64[idx] = pv;
                 else bt16[idx] = f32_to_bf16((float)pv);
@@ -920,6 +997,12 @@ void build_kernel_matrices(Plan& P, const std::vector<SysInput>& in, hipStream_t
 bool refresh_ordinates(Plan& P, const std::vector<SysInput>& in, hipStream_t s)
 {
     if ((int)in.size() != P.nsys) return false;
+    int mom_r = 0;
+    for (auto& si : in) {
+        if ((scat_mode(si.h) == 1) != (P.nmom == 4) || (scat_mode(si.h) == 2) != P.aniso) return false;
+        if (scat_mode(si.h) == 1 && si.h->scat_norm) mom_r = 1;
+    }
+    if (mom_r != P.mom_r) return false;
     std::vector<std::array<std::vector<int>, 4>> ql(in.size());
     for (size_t k = 0; k < in.size(); ++k) {
         if (in[k].h != P.handles[P.sys[k].prob]) return false;
@@ -958,11 +1041,7 @@ bool refresh_ordinates(Plan& P, const std::vector<SysInput>& in, hipStream_t s)
                         const int u = b0 + o < list.size() ? list[b0 + o] : -1;
                         ld.ord = (int)uo.size();
                         uo.push_back(u);
-                        ld.a = ld.b = ld.w = 0.0;
-                        if (u < 0) continue;
-                        ld.a = std::fabs(in[k].dirs[3 * u]) / h->dx;
-                        ld.b = std::fabs(in[k].dirs[3 * u + 1]) / h->dy;
-                        ld.w = in[k].w[u];
+                        fill_lane(ld, h, in[k], u, {});
                     }
                 }
             }
@@ -996,22 +1075,28 @@ bool refresh_ordinates(Plan& P, const std::vector<SysInput>& in, hipStream_t s)
         P.sys_n[k] = in[k].n;
         P.sys_w[k] = in[k].w;
     }
+    std::vector<std::vector<double>> inv_r(P.nsys);
+    for (int k = 0; k < P.nsys; ++k) inv_r[k] = linear_inv_r(in[k].h, in[k]);
     for (int k = 0; k < P.nws; ++k) {
         const WaveStreamDev& W = P.ws[k];
         rom_handle* h = P.handles[W.prob];
         for (int lane = 0; lane < kWave; ++lane) {
             LaneDev& ld = P.lanes[(size_t)k * kWave + lane];
             const int sy = W.sys[lane / W.L];
-            ld.a = ld.b = ld.w = 0.0;
-            if (sy < 0) continue;
-            const int u = P.user_of[sy][ld.ord];
-            if (u < 0) continue;
-            ld.a = std::fabs(in[sy].dirs[3 * u]) / h->dx;
-            ld.b = std::fabs(in[sy].dirs[3 * u + 1]) / h->dy;
-            ld.w = in[sy].w[u];
+            fill_lane(ld, h, in[sy < 0 ? 0 : sy], sy < 0 ? -1 : P.user_of[sy][ld.ord], sy < 0 ? inv_r[0] : inv_r[sy]);
         }
     }
     rewrite(P.d_lanes, P.lanes, s);
+    // the linear kernel's g may have changed
+    bool gchange = false;
+    for (int k = 0; k < P.nsys; ++k) {
+        const double g = scat_mode(in[k].h) == 1 ? in[k].h->g : 0.0;
+        if (P.sys[k].g != g) {
+            P.sys[k].g = g;
+            gchange = true;
+        }
+    }
+    if (gchange) rewrite(P.d_sys, P.sys, s);
     if (P.inflow_len > 0) {
         P.h_inflow = inflow_table(P, in);
         if (P.fp64) {
@@ -1077,10 +1162,11 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
-    // initial state: phi = 0, isotropic source = q, angular flux = 0
+    // initial state: phi = 0, isotropic source = q (linear kernel: S0 = q, S1 = S2 = 0), angular flux = 0
     int64_t phi_total = 0;
     for (auto& sd : P.sys) phi_total = std::max<int64_t>(phi_total, sd.phi_off + P.handles[sd.prob]->cells);
     HIPCHK(launch_fill(P.d_phi.p, phi_total, P.fp64, 0.0, s));
+    if (P.nmom == 4) HIPCHK(launch_fill(P.src_ptr(), P.src_len, P.fp64, 0.0, s));  // S1 = S2 = 0
     for (auto& sd : P.sys) {
         const int64_t cells = P.handles[sd.prob]->cells;
         HIPCHK(hipMemcpyAsync(P.src_ptr() + sd.src_off * P.esz, (char*)P.d_q.p + P.probs[sd.prob].field_off * P.esz,
@@ -1198,11 +1284,12 @@ int validate_opts(rom_handle* h, const rom_si_opts* o, rom_si_opts& out)
     return ROM_OK;
 }
 
-std::string plan_signature(const rom_si_opts& o, bool aniso, int kind, int nsys)
+// sig: scat_sig of the handle (or of the batch's first handle; every member matches it)
+std::string plan_signature(const rom_si_opts& o, int sig, int kind, int nsys)
 {
     char buf[256];
     std::snprintf(buf, sizeof buf, "k%d p%d s%d t%dx%d b%d a%d n%d mi%d w%d r%d q%d", kind, o.precision, o.scheme, o.tile_x,
-                  o.tile_y, o.band, (int)aniso, nsys, o.max_iter, o.sweep, o.diag_rows, o.diag_k);
+                  o.tile_y, o.band, sig, nsys, o.max_iter, o.sweep, o.diag_rows, o.diag_k);
     return buf;
 }
 
@@ -1327,6 +1414,7 @@ int rom_set_ordinates(rom_handle* h, int32_t n, const double* dirs, const double
     for (auto& a : h->ang) a.clear();
     if (h->scat == ROM_SCAT_DENSE) {
         h->scat = ROM_SCAT_ISO;
+        h->scat_norm = false;
         h->Pdense.clear();
     }
     h->version++;
@@ -1354,6 +1442,8 @@ int rom_set_inflow_angular(rom_handle* h, int32_t face, const double* vals)
 int rom_set_scattering(rom_handle* h, int32_t kind, double g, const double* P)
 {
     if (!h) return ROM_E_ARG;
+    const bool norm = (kind & ROM_SCAT_NORMALIZE) != 0;
+    kind &= ~ROM_SCAT_NORMALIZE;
     if (kind < ROM_SCAT_ISO || kind > ROM_SCAT_DENSE) return fail(h, ROM_E_ARG, "bad scattering kind");
     if (!isfin(g)) return fail(h, ROM_E_DOMAIN, "g must be finite");
     if (kind == ROM_SCAT_HG && !(std::fabs(g) < 1.0)) return fail(h, ROM_E_DOMAIN, "HG needs |g| < 1");
@@ -1369,6 +1459,7 @@ int rom_set_scattering(rom_handle* h, int32_t kind, double g, const double* P)
         h->Pdense.clear();
     }
     h->scat = kind;
+    h->scat_norm = norm;
     h->g = g;
     h->version++;
     return ROM_OK;
@@ -1400,7 +1491,7 @@ int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double
         std::vector<SysInput> in{{h, h->dirs.data(), h->w.data(), h->n, true}};
         std::unique_ptr<Plan> P(new Plan());
         if (o.sweep == ROM_SWEEP_AUTO) o.sweep = ROM_SWEEP_STRIP;
-        build_plan(*P, in, o, per, 0, psi != nullptr);
+        build_plan(*P, in, o, per ? 2 : 0, 0, psi != nullptr);
         hipStream_t s = h->stream();
         const SystemDev& sd = P->sys[0];
         const int al = P->npad_al[0];
@@ -1435,7 +1526,7 @@ int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double
         } else {
             SweepArgs sa = P->sweep_args(1, psi_mode);
             // the sweep writes psi' into the angular layout when asked for it
-            HIPCHK(launch_sweep(sa, P->grid, P->fp64, P->tx, P->ty, P->dd, per, psi_mode, P->L, s));
+            HIPCHK(launch_sweep(sa, P->grid, P->fp64, P->tx, P->ty, P->dd, per, psi_mode, P->L, 1, s));
         }
         const CombineArgs ca = P->combine_args(1, 0.0);
         HIPCHK(launch_combine(ca, (int)P->cblocks.size(), P->fp64, s));
@@ -1475,7 +1566,7 @@ int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double
 
 namespace {
 
-bool is_aniso(const rom_handle* h) { return h->scat != ROM_SCAT_ISO; }
+bool is_aniso(const rom_handle* h) { return scat_mode(h) == 2; }
 
 // Source iteration for a list of systems; fills stats and phis.
 // ------------------------------------------------------------------------------------ autotuner
@@ -1487,7 +1578,7 @@ bool is_aniso(const rom_handle* h) { return h->scat != ROM_SCAT_ISO; }
 // warm-up and two timed sweeps each) and caches the fastest for the process.  Every choice is
 // deterministic; strip tiles and bands give bitwise identical results, while the row-lane kernel
 // sums the ordinates of a cell in another (fixed) order.
-std::string tune_key(const std::vector<SysInput>& in, const rom_si_opts& o, bool aniso)
+std::string tune_key(const std::vector<SysInput>& in, const rom_si_opts& o, int smode)
 {
     int maxnx = 0, maxny = 0, maxn = 0;
     int64_t work = 0;
@@ -1498,7 +1589,7 @@ std::string tune_key(const std::vector<SysInput>& in, const rom_si_opts& o, bool
         work += s.h->cells * (int64_t)s.n;
     }
     char buf[160];
-    std::snprintf(buf, sizeof buf, "p%d s%d a%d k%zu x%d y%d n%d w%lld v%d r%d q%d", o.precision, o.scheme, (int)aniso,
+    std::snprintf(buf, sizeof buf, "p%d s%d a%d k%zu x%d y%d n%d w%lld v%d r%d q%d", o.precision, o.scheme, smode,
                   in.size(), maxnx, maxny, maxn, (long long)work, o.sweep, o.diag_rows, o.diag_k);
     return buf;
 }
@@ -1531,10 +1622,11 @@ void apply_choice(const TuneChoice& c, rom_si_opts& o)
 // Time three sweep + combine steps of every candidate on the real buffers of this batch shape
 // (zero sources) and keep the fastest for the process.  Candidates: the strip kernel's tiles x bands, and, for
 // isotropic step-scheme problems, the row-lane kernel's (rows, ordinates per lane).
-void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t s)
+void autotune(std::vector<SysInput>& in, rom_si_opts& o, int smode, hipStream_t s)
 {
     static std::map<std::string, TuneChoice> cache;
-    const std::string key = tune_key(in, o, aniso);
+    const bool aniso = smode == 2;
+    const std::string key = tune_key(in, o, smode);
     auto it = cache.find(key);
     if (it != cache.end()) {
         apply_choice(it->second, o);
@@ -1548,7 +1640,7 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t
         for (auto t : tiles)
             for (int band : {2, 4, 8}) cands.push_back({ROM_SWEEP_STRIP, t.first, t.second, band, 0, 0});
     }
-    if (o.sweep != ROM_SWEEP_STRIP && !aniso && o.scheme == ROM_SCHEME_STEP) {
+    if (o.sweep != ROM_SWEEP_STRIP && smode == 0 && o.scheme == ROM_SCHEME_STEP) {
         for (int rows : {16, 64})
             for (int k : {1, 2, 4})
                 if (diag_supported(fp64, rows, k) && (o.diag_rows == 0 || o.diag_rows == rows) && (o.diag_k == 0 || o.diag_k == k))
@@ -1565,16 +1657,14 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t
         apply_choice(cand, c);
         Plan P;
         try {
-            build_plan(P, in, c, aniso, 1);
+            build_plan(P, in, c, smode, 1);
         } catch (const Fail&) {
             continue;  // does not fit (LDS) or not supported for this batch
         }
         if (cand.sweep == ROM_SWEEP_STRIP &&
-            (P.band != cand.band || sweep_lds_bytes(P.fp64, P.tx, P.ty, aniso, P.L, P.band) > 64 * 1024))
+            (P.band != cand.band || sweep_lds_bytes(P.fp64, P.tx, P.ty, aniso, P.L, P.band, P.nmom) > 64 * 1024))
             continue;
-        int64_t tot = 0;
-        for (auto& sd : P.sys) tot = std::max<int64_t>(tot, sd.phi_off + P.handles[sd.prob]->cells);
-        HIPCHK(launch_fill(P.src_ptr(), tot, P.fp64, 0.0, s));
+        HIPCHK(launch_fill(P.src_ptr(), P.src_len, P.fp64, 0.0, s));
         if (aniso) HIPCHK(launch_fill(P.d_ang.p, (int64_t)(P.d_ang.bytes / P.esz), P.fp64, 0.0, s));
         float ms = 0.f;
         const CombineArgs ca = P.combine_args(1, 0.0);
@@ -1614,17 +1704,19 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, bool aniso, hipStream_t
 int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opts& o_in, int reuse,
                   std::unique_ptr<Plan>& slot, SolveResult& res)
 {
-    const bool aniso = is_aniso(in[0].h);
+    const int smode = scat_mode(in[0].h);
+    const bool aniso = smode == 2;
     for (auto& s : in)
-        if (is_aniso(s.h) != aniso) return fail(owner, ROM_E_ARG, "batched problems must all be isotropic or all anisotropic");
+        if (scat_mode(s.h) != smode)
+            return fail(owner, ROM_E_ARG, "batched problems must share the scattering mode (isotropic, linear or dense)");
     rom_si_opts o = o_in;
     if (reuse == 2 && slot && !refresh_ordinates(*slot, in, owner->stream())) reuse = 0;
     if (reuse == 0 || !slot) {
         const bool free_shape = o.sweep == ROM_SWEEP_DIAG ? (o.diag_rows == 0 || o.diag_k == 0 || o.band == 0)
                                                           : (o.tile_x == 0 && o.band == 0);
-        if (free_shape && autotune_enabled()) autotune(in, o, aniso, owner->stream());
+        if (free_shape && autotune_enabled()) autotune(in, o, smode, owner->stream());
         slot.reset(new Plan());
-        build_plan(*slot, in, o, aniso, o.max_iter);
+        build_plan(*slot, in, o, smode, o.max_iter);
         if (aniso) build_kernel_matrices(*slot, in);
     }
     res = run_si(*slot, owner->stream(), o);
@@ -1645,7 +1737,7 @@ int rom_source_iterate(rom_handle* h, const rom_si_opts* opts, double* phi, rom_
     if (rc) return rc;
     try {
         std::vector<SysInput> in{{h, h->dirs.data(), h->w.data(), h->n, true}};
-        const std::string sig = plan_signature(o, is_aniso(h), 0, 1);
+        const std::string sig = plan_signature(o, scat_sig(h), 0, 1);
         const int reuse = !(h->plan && h->plan_sig == sig) ? 0 : h->plan_version == h->version ? 1 : 2;
         if (!reuse) h->plan.reset();
         SolveResult res;
@@ -1704,7 +1796,7 @@ int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, d
         for (int i = 0; i < k; ++i) in.push_back({hs[i], hs[i]->dirs.data(), hs[i]->w.data(), hs[i]->n, true});
         // the batch plan is reused for the same handles in the same order (refreshed if any of
         // them changed ordinates, inflow or kernel since)
-        std::string key = plan_signature(o, is_aniso(h0), 1, k), vers;
+        std::string key = plan_signature(o, scat_sig(h0), 1, k), vers;
         for (int i = 0; i < k; ++i) {
             key += " " + std::to_string(hs[i]->uid);
             vers += " " + std::to_string(hs[i]->version);
@@ -1791,7 +1883,7 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
                 in.push_back({h, dirs.data() + (size_t)(done + k) * 3 * n, w.data() + (size_t)(done + k) * n, n, false});
             char kb[96];
             std::snprintf(kb, sizeof kb, " e%d %d %d %d", spec->kind, n, b, h->scat);
-            const std::string key = plan_signature(o, aniso, 2, b) + kb;
+            const std::string key = plan_signature(o, scat_sig(h), 2, b) + kb;
             const int reuse = (P && h->ens_key == key) ? 2 : 0;
             if (!reuse) P.reset();
             h->ens_key.clear();

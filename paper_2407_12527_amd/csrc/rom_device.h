@@ -47,8 +47,11 @@ struct WaveStreamDev {
     int32_t slot[kMaxGroups];   // partial-flux slot of each group (-1: empty group)
 };
 
-struct LaneDev {                // per (wave-stream, lane); padded lanes have w = a = b = 0
+struct LaneDev {                // per (wave-stream, lane); padded lanes are all zero
     double a, b, w;             // |c|/dx, |s|/dy, quadrature weight
+    double c, s;                // signed direction cosines (linear-kernel source c S1 + s S2)
+    double m1, m2, m3;          // linear-kernel moment weights c / r, s / r, 1 / r (r: the row sum
+                                // of the normalized kernel, 1 without normalization)
     int32_t ord;                // internal (padded, quadrant-grouped) ordinate index in its system
     int32_t pad;
 };
@@ -59,8 +62,10 @@ struct SystemDev {
     int32_t nslots;             // partial slots summed by the combine step, in this order
     int32_t slot_first;         // index into the slot-order list
     int64_t phi_off;            // scalar flux [cells] (elements of T)
-    int64_t src_off;            // isotropic source [cells] (elements of T)
+    int64_t src_off;            // isotropic source [cells] (elements of T); with the linear
+                                // kernel three planes [3][cells]: S0, S1, S2 of S0 + c S1 + s S2
     int64_t ang_off;            // anisotropic source / angular flux [cells][npad] (elements)
+    double g;                   // linear-kernel anisotropy (S1, S2 = sigma_s g Jx~, sigma_s g Jy~)
 };
 
 // Task of the row-lane ("diagonal") sweep: the whole grid of one problem for NO = (64 / R) * K

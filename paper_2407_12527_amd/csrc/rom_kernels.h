@@ -30,6 +30,8 @@ struct SweepArgs {
     long long* prog;           // strip progress counters
     Ctl* ctl;
     SysCtl* sysctl;
+    int32_t mom_r;             // linear kernel: 1 = also form the 1/r-weighted density (plane 3)
+    int32_t pad;
 };
 
 struct DiagArgs {
@@ -63,9 +65,12 @@ struct CombineArgs {
     int32_t many_cpt;          // 0: one wave sums all slots of 4 cells per thread; 1, 2, 4, 8: the
                                // many-slot combine, tiles of 64 * many_cpt cells (= cells_per_block)
     int32_t nsys;
-    int32_t pad0;
+    int32_t nmom;              // partial planes per slot: 1 (phi) or 4 (linear kernel: phi, Jx~,
+                               // Jy~, phi~); sources: 1 or 3 planes
     int32_t mode;              // 0: source-iteration step, 1: plain sum (single sweep)
     int32_t max_iter;
+    int32_t mom_r;             // linear kernel: phi~ comes from plane 3 (else phi~ = phi)
+    int32_t pad0;
     double tol;
     const void* part;
     void* phi;
@@ -99,12 +104,13 @@ struct ContractArgs {
     const SysCtl* sysctl;      // skip when that system has stopped (NULL: always run)
 };
 
-// L = lanes per ordinate group (16, 32 or 64; 64 for anisotropic sources and psi output)
+// L = lanes per ordinate group (16, 32 or 64; 64 for anisotropic sources and psi output);
+// mom = 1 (isotropic source) or 4 (linear kernel: three source planes, four moment planes)
 hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty, bool dd, bool ang, int psi, int L,
-                        hipStream_t s);
+                        int mom, hipStream_t s);
 bool sweep_tile_supported(int tx, int ty);
 bool sweep_tile_supported_fp64(int tx, int ty);
-size_t sweep_lds_bytes(bool fp64, int tx, int ty, bool ang, int L, int nw);
+size_t sweep_lds_bytes(bool fp64, int tx, int ty, bool ang, int L, int nw, int mom);
 // Row-lane sweep: R rows per lane block (16 or 64), K ordinates per lane (1, 2, 4; FP64: 1, 2),
 // nb wavefronts (row blocks) per workgroup (1..16; 1..8 when K * sizeof(T) >= 16), persistent
 // workgroups taking (task, band) tickets.

@@ -4,6 +4,7 @@
 //   combine_kernel   phi = sum of the per-group partial fluxes in a fixed order, the next
 //                    isotropic source sigma_s phi + q, the FP64 relative change and the
 //                    per-system convergence decision of source iteration (eq. (3.10));
+//                    combine_moments_kernel does the same for the linear kernel's moments;
 //   contract_*       anisotropic scattering source S = sigma_s (Psi' P) + q (eq. (3.1) right-hand
 //                    side with W = w P of eq. (3.4)): BF16 MFMA with FP32 accumulation, or a plain
 //                    tiled FP64/FP32 kernel for the FP64 path;
@@ -209,6 +210,60 @@ __global__ __launch_bounds__(256) void combine_many_kernel(CombineArgs A)
                 pmax = fmax(pmax, fabs((double)v));
                 phi[cell] = v;
                 src[cell] = fma(ss[cell], v, q[cell]);
+            }
+        }
+    }
+    combine_tail(A, run, s, dmax, pmax);
+}
+
+// Combine of the linear-kernel sweep (four partial planes per slot: phi, Jx~, Jy~, phi~): per
+// cell the fixed-order sums over the system's slots, phi, its change, and the three source planes
+// of the next sweep, S0 = sigma_s phi~ + q, S1 = sigma_s g Jx~, S2 = sigma_s g Jy~ (the folded
+// kernel 1 + g (c c' + s s') of eq. (2.1) contracted through its moments).  Without
+// normalization, or on a mirror-symmetric set, phi~ = phi and plane 3 is not formed.
+template <typename T>
+__global__ __launch_bounds__(256) void combine_moments_kernel(CombineArgs A)
+{
+    const int tid = threadIdx.x;
+    if (A.mode == 0 && A.ctl->active == 0) return;
+    const int2 blk = A.blocks[blockIdx.x];
+    const int s = blk.x;
+    const SystemDev& SD = A.sys[s];
+    const ProblemDev& P = A.probs[SD.prob];
+    const int cells = P.nx * P.ny;
+    const bool run = A.mode == 1 || A.sysctl[s].state == 0;
+    double dmax = 0.0, pmax = 0.0;
+    if (run) {
+        const T* __restrict__ part = (const T*)A.part;
+        T* __restrict__ phi = (T*)A.phi + SD.phi_off;
+        T* __restrict__ src = (T*)A.src + SD.src_off;
+        const T* __restrict__ ss = (const T*)A.sigma_s + P.field_off;
+        const T* __restrict__ q = (const T*)A.q + P.field_off;
+        const int ns = SD.nslots;
+        const int64_t* __restrict__ soff = A.slot_off;
+        const int32_t* __restrict__ sord = A.slot_order + SD.slot_first;
+        const int c1 = min(cells, blk.y + A.cells_per_block);
+        const T g = (T)SD.g;
+        const int64_t pl = cells;
+        for (int cell = blk.y + tid; cell < c1; cell += 256) {
+            T v0 = T(0), v1 = T(0), v2 = T(0), v3 = T(0);
+            for (int k = 0; k < ns; ++k) {
+                const T* __restrict__ pk = part + soff[sord[k]] + cell;
+                v0 += pk[0];
+                v1 += pk[pl];
+                v2 += pk[2 * pl];
+                if (A.mom_r) v3 += pk[3 * pl];
+            }
+            if (!A.mom_r) v3 = v0;
+            const T old = phi[cell];
+            dmax = fmax(dmax, fabs((double)v0 - (double)old));
+            pmax = fmax(pmax, fabs((double)v0));
+            phi[cell] = v0;
+            if (A.mode == 0) {
+                const T sg = ss[cell] * g;
+                src[cell] = fma(ss[cell], v3, q[cell]);
+                src[pl + cell] = sg * v1;
+                src[2 * pl + cell] = sg * v2;
             }
         }
     }
@@ -459,18 +514,18 @@ __global__ void cast_bf16_kernel(const float* __restrict__ in, __hip_bfloat16* _
 }
 
 // ------------------------------------------------------------------------------------ launchers
-hipError_t launch_sweep_f32_8x4(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
-hipError_t launch_sweep_f32_8x8(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
-hipError_t launch_sweep_f32_16x8(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
-hipError_t launch_sweep_f32_16x16(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
-hipError_t launch_sweep_f64_8x4(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
-hipError_t launch_sweep_f64_8x8(const SweepArgs&, int, bool, bool, int, int, hipStream_t);
+hipError_t launch_sweep_f32_8x4(const SweepArgs&, int, bool, bool, int, int, int, hipStream_t);
+hipError_t launch_sweep_f32_8x8(const SweepArgs&, int, bool, bool, int, int, int, hipStream_t);
+hipError_t launch_sweep_f32_16x8(const SweepArgs&, int, bool, bool, int, int, int, hipStream_t);
+hipError_t launch_sweep_f32_16x16(const SweepArgs&, int, bool, bool, int, int, int, hipStream_t);
+hipError_t launch_sweep_f64_8x4(const SweepArgs&, int, bool, bool, int, int, int, hipStream_t);
+hipError_t launch_sweep_f64_8x8(const SweepArgs&, int, bool, bool, int, int, int, hipStream_t);
 
-size_t sweep_lds_bytes(bool fp64, int tx, int ty, bool ang, int L, int nw)
+size_t sweep_lds_bytes(bool fp64, int tx, int ty, bool ang, int L, int nw, int mom)
 {
     const size_t esz = fp64 ? 8 : 4;
     const size_t ch = (size_t)tx * ty;
-    const size_t ngd = ang ? 1 : (size_t)(kWave / L);
+    const size_t ngd = ang ? 1 : (size_t)(kWave / L) * (mom == 4 ? 3 : 1);
     return esz * ((size_t)nw * (ch + ngd * (ch + 4)) + (size_t)(nw > 1 ? nw - 1 : 1) * kRingSlots * tx * kWave) +
            sizeof(int) * (2 * kMaxBand + 1);
 }
@@ -483,18 +538,18 @@ bool sweep_tile_supported(int tx, int ty)
 bool sweep_tile_supported_fp64(int tx, int ty) { return tx == 8 && (ty == 4 || ty == 8); }
 
 hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty, bool dd, bool ang, int psi, int L,
-                        hipStream_t s)
+                        int mom, hipStream_t s)
 {
     if (fp64) {
         if (psi == 2) return hipErrorInvalidValue;
-        if (tx == 8 && ty == 4) return launch_sweep_f64_8x4(a, grid, dd, ang, psi, L, s);
-        if (tx == 8 && ty == 8) return launch_sweep_f64_8x8(a, grid, dd, ang, psi, L, s);
+        if (tx == 8 && ty == 4) return launch_sweep_f64_8x4(a, grid, dd, ang, psi, L, mom, s);
+        if (tx == 8 && ty == 8) return launch_sweep_f64_8x8(a, grid, dd, ang, psi, L, mom, s);
         return hipErrorInvalidValue;
     }
-    if (tx == 8 && ty == 4) return launch_sweep_f32_8x4(a, grid, dd, ang, psi, L, s);
-    if (tx == 8 && ty == 8) return launch_sweep_f32_8x8(a, grid, dd, ang, psi, L, s);
-    if (tx == 16 && ty == 8) return launch_sweep_f32_16x8(a, grid, dd, ang, psi, L, s);
-    if (tx == 16 && ty == 16) return launch_sweep_f32_16x16(a, grid, dd, ang, psi, L, s);
+    if (tx == 8 && ty == 4) return launch_sweep_f32_8x4(a, grid, dd, ang, psi, L, mom, s);
+    if (tx == 8 && ty == 8) return launch_sweep_f32_8x8(a, grid, dd, ang, psi, L, mom, s);
+    if (tx == 16 && ty == 8) return launch_sweep_f32_16x8(a, grid, dd, ang, psi, L, mom, s);
+    if (tx == 16 && ty == 16) return launch_sweep_f32_16x16(a, grid, dd, ang, psi, L, mom, s);
     return hipErrorInvalidValue;
 }
 
@@ -528,6 +583,13 @@ hipError_t launch_diag(const DiagArgs& a, int grid, int nb, bool fp64, int R, in
 
 hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s)
 {
+    if (a.nmom == 4) {
+        if (a.many_cpt != 0) return hipErrorInvalidValue;
+        if (fp64) hipLaunchKernelGGL(combine_moments_kernel<double>, dim3(nblocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(combine_moments_kernel<float>, dim3(nblocks), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
+    if (a.nmom != 1) return hipErrorInvalidValue;
     if (a.many_cpt > 0) {
         // block tiles of 64 * many_cpt cells (cells_per_block must match)
         if (a.cells_per_block != 64 * a.many_cpt) return hipErrorInvalidValue;

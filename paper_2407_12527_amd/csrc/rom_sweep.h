@@ -21,6 +21,11 @@ namespace rom {
 // and staged in LDS in sweep order, so the row loop reads LDS broadcasts only.  A ragged chunk or
 // strip is padded with a valid cell and a zero source; padded results are never stored.
 //
+// Linear kernel (MOM = 4): the source of lane l is S0 + c_l S1 + s_l S2 (three staged planes),
+// and besides phi the row is reduced three more times with the lane weights c/r, s/r and 1/r
+// (Jx~, Jy~ and, when the kernel is normalized on an asymmetric set, phi~) into planes 1..3 of
+// the lane group's partial slot.
+//
 // Scalar flux: the TX values of a row are summed over each group's lanes by a transposing
 // butterfly (gfx950 permlane swaps for lane distances 32 and 16, DPP for 8, 4, 2, 1): every
 // stage halves the number of registers, so a row of TX cells costs about 2 VALU operations per
@@ -151,13 +156,15 @@ __device__ __forceinline__ void store_partials(const RowCtx& R, double (&acc)[TX
 // strips of one wave-stream: wave k sweeps strip band*NW + k.  Edges between strips of a band go
 // through LDS ring buffers (RB chunk slots per boundary, produced / consumed counters in LDS);
 // only the band's top edge goes to global memory for the next band, behind a progress counter.
-template <typename T, int TX, int TY, bool DD, bool ANG, int PSI, int L>
+template <typename T, int TX, int TY, bool DD, bool ANG, int PSI, int L, int MOM>
 __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
 {
+    static_assert(MOM == 1 || (MOM == 4 && !ANG && PSI == 0), "moment sweeps take staged sources only");
     constexpr int G = kWave / L;  // lane groups per wavefront
     constexpr int CH = TX * TY;
     constexpr int PER = (CH + kWave - 1) / kWave;
-    constexpr int NG = ANG ? 0 : kWave / L;  // staged isotropic sources, one block per group
+    constexpr int NSRC = MOM == 4 ? 3 : 1;             // source planes per group
+    constexpr int NG = ANG ? 0 : (kWave / L) * NSRC;   // staged source blocks (group-major)
     constexpr int NGD = NG > 0 ? NG : 1;
     constexpr int RB = kRingSlots;
     const int wave = threadIdx.x >> 6;
@@ -208,6 +215,7 @@ __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
         const ProblemDev& Pg = A.probs[wprob];
         const int nx = uniform(Pg.nx), ny = uniform(Pg.ny), nchunks = uniform(Pg.nchunks), nstrips = uniform(Pg.nstrips);
         const int64_t field_off = uniform64(Pg.field_off), uflag_off = uniform64(Pg.uflag_off);
+        const int64_t plane = (int64_t)nx * ny;  // source and partial planes of the linear kernel
         const int strip = band * NW + wave;
 
         // skip wave-streams whose systems have all stopped (flags change only between sweeps)
@@ -229,6 +237,9 @@ __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
             const T b = to_T<T>(DD ? 2.0 * ld.b : ld.b);
             const T w = to_T<T>(ld.w);
             const T kappa = a + b;
+            // linear kernel: source direction cosines and moment weights of this lane
+            const T lc = to_T<T>(ld.c), ls = to_T<T>(ld.s);
+            const T m1 = to_T<T>(ld.m1), m2 = to_T<T>(ld.m2), m3 = to_T<T>(ld.m3);
             const SystemDev& SD = A.sys[gsys];
             const T* __restrict__ Ap = angp + SD.ang_off + ld.ord;
             const int64_t npad = SD.npad;
@@ -300,7 +311,8 @@ __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
                         if constexpr (NG > 0) {
 #pragma unroll
                             for (int q = 0; q < NG; ++q) {
-                                const T v = sbase[q][cell];  // clamped cell: always a valid address
+                                // clamped cell: always a valid address
+                                const T v = sbase[q / NSRC][(q % NSRC) * plane + cell];
                                 pS[q][k] = inside ? v : T(0);
                             }
                         }
@@ -359,6 +371,12 @@ __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
                     if constexpr (ANG) {
 #pragma unroll
                         for (int i = 0; i < TX; ++i) Sv[i] = cA[r * TX + i];
+                    } else if constexpr (MOM == 4) {
+                        const T* s0 = lds_S[wave][g * NSRC];
+                        const T* s1 = lds_S[wave][g * NSRC + 1];
+                        const T* s2 = lds_S[wave][g * NSRC + 2];
+#pragma unroll
+                        for (int i = 0; i < TX; ++i) Sv[i] = fma(ls, s2[r * TX + i], fma(lc, s1[r * TX + i], s0[r * TX + i]));
                     } else {
 #pragma unroll
                         for (int i = 0; i < TX; ++i) Sv[i] = lds_S[wave][g][r * TX + i];
@@ -412,7 +430,22 @@ __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
                         }
                     }
                     const RowCtx R{lane, g, rowbase, i0, nx, xpos, cols};
-                    store_partials<TX, L>(R, acc, my_part);
+                    if constexpr (MOM == 4) {
+                        // moments first: the FP64 reduction works in place on its input
+                        T a1[TX], a2[TX], a3[TX];
+#pragma unroll
+                        for (int i = 0; i < TX; ++i) {
+                            a1[i] = acc[i] * m1;
+                            a2[i] = acc[i] * m2;
+                            a3[i] = acc[i] * m3;
+                        }
+                        store_partials<TX, L>(R, acc, my_part);
+                        store_partials<TX, L>(R, a1, my_part ? my_part + plane : nullptr);
+                        store_partials<TX, L>(R, a2, my_part ? my_part + 2 * plane : nullptr);
+                        if (A.mom_r) store_partials<TX, L>(R, a3, my_part ? my_part + 3 * plane : nullptr);
+                    } else {
+                        store_partials<TX, L>(R, acc, my_part);
+                    }
                 };
                 if constexpr (ANG) {
 #pragma unroll
@@ -444,34 +477,42 @@ __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
 }
 
 
-inline size_t sweep_lds_bytes_t(size_t esz, int tx, int ty, bool ang, int L, int nw)
+inline size_t sweep_lds_bytes_t(size_t esz, int tx, int ty, bool ang, int L, int nw, int mom)
 {
     const size_t ch = (size_t)tx * ty;
-    const size_t ngd = ang ? 1 : (size_t)(kWave / L);
+    const size_t ngd = ang ? 1 : (size_t)(kWave / L) * (mom == 4 ? 3 : 1);
     return esz * ((size_t)nw * (ch + ngd * (ch + 4)) + (size_t)(nw > 1 ? nw - 1 : 1) * kRingSlots * tx * kWave) +
            sizeof(int) * (2 * kMaxBand + 1);
 }
 
-template <typename T, int TX, int TY, bool DD, bool ANG, int PSI, int L>
+template <typename T, int TX, int TY, bool DD, bool ANG, int PSI, int L, int MOM = 1>
 hipError_t launch_sweep_t(const SweepArgs& a, int grid, hipStream_t s)
 {
     if (a.band < 1 || a.band > kMaxBand) return hipErrorInvalidValue;
-    const size_t lds = sweep_lds_bytes_t(sizeof(T), TX, TY, ANG, L, a.band);
+    const size_t lds = sweep_lds_bytes_t(sizeof(T), TX, TY, ANG, L, a.band, MOM);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute((const void*)sweep_kernel<T, TX, TY, DD, ANG, PSI, L>,
+        const hipError_t e = hipFuncSetAttribute((const void*)sweep_kernel<T, TX, TY, DD, ANG, PSI, L, MOM>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((sweep_kernel<T, TX, TY, DD, ANG, PSI, L>), dim3(grid), dim3(64 * a.band), lds, s, a);
+    hipLaunchKernelGGL((sweep_kernel<T, TX, TY, DD, ANG, PSI, L, MOM>), dim3(grid), dim3(64 * a.band), lds, s, a);
     return hipGetLastError();
 }
 
 // Dispatch over scheme, source kind, angular-flux output and lane-group size for one tile shape.
 // Anisotropic sources and angular-flux output always use 64-lane groups.
 template <typename T, int TX, int TY>
-hipError_t launch_sweep_tile(const SweepArgs& a, int grid, bool dd, bool ang, int psi, int L, hipStream_t s)
+hipError_t launch_sweep_tile(const SweepArgs& a, int grid, bool dd, bool ang, int psi, int L, int mom, hipStream_t s)
 {
+    if (mom == 4) {
+        if (ang || psi) return hipErrorInvalidValue;
+        if (L == 64) return dd ? launch_sweep_t<T, TX, TY, true, false, 0, 64, 4>(a, grid, s) : launch_sweep_t<T, TX, TY, false, false, 0, 64, 4>(a, grid, s);
+        if (L == 32) return dd ? launch_sweep_t<T, TX, TY, true, false, 0, 32, 4>(a, grid, s) : launch_sweep_t<T, TX, TY, false, false, 0, 32, 4>(a, grid, s);
+        if (L == 16) return dd ? launch_sweep_t<T, TX, TY, true, false, 0, 16, 4>(a, grid, s) : launch_sweep_t<T, TX, TY, false, false, 0, 16, 4>(a, grid, s);
+        return hipErrorInvalidValue;
+    }
+    if (mom != 1) return hipErrorInvalidValue;
     if (ang || psi) {
         if (L != 64) return hipErrorInvalidValue;
         if (ang) {

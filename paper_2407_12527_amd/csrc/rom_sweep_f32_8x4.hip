@@ -3,9 +3,9 @@
 
 namespace rom {
 
-hipError_t launch_sweep_f32_8x4(const SweepArgs& a, int grid, bool dd, bool ang, int psi, int L, hipStream_t s)
+hipError_t launch_sweep_f32_8x4(const SweepArgs& a, int grid, bool dd, bool ang, int psi, int L, int mom, hipStream_t s)
 {
-    return launch_sweep_tile<float, 8, 4>(a, grid, dd, ang, psi, L, s);
+    return launch_sweep_tile<float, 8, 4>(a, grid, dd, ang, psi, L, mom, s);
 }
 
 }  // namespace rom

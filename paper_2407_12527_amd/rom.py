@@ -16,7 +16,7 @@ import numpy as np
 __all__ = [
     "ROM_OK", "ROM_NOT_CONVERGED", "ROM_E_ARG", "ROM_E_DOMAIN", "ROM_E_STATE", "ROM_E_NOMEM", "ROM_E_DEVICE",
     "ROM_E_DIVERGED", "ROM_E_UNSUPPORTED", "ROM_SCHEME_STEP", "ROM_SCHEME_DD", "ROM_SCAT_ISO", "ROM_SCAT_LINEAR",
-    "ROM_SCAT_HG", "ROM_SCAT_DENSE", "ROM_ORD_STRATIFIED", "ROM_ORD_IID_SPHERE", "ROM_ORD_UNIFORM2D",
+    "ROM_SCAT_HG", "ROM_SCAT_DENSE", "ROM_SCAT_NORMALIZE", "ROM_ORD_STRATIFIED", "ROM_ORD_IID_SPHERE", "ROM_ORD_UNIFORM2D",
     "ROM_ORD_GAUSS2D", "ROM_PREC_FP32", "ROM_PREC_FP64", "ROM_FACE_LEFT", "ROM_FACE_RIGHT", "ROM_FACE_BOTTOM",
     "ROM_FACE_TOP", "rom_grid", "rom_inflow", "rom_ord_spec", "rom_si_opts", "rom_si_stats", "rom_ens_stats",
     "RomError", "Handle", "lib", "library_path", "EXPORTS", "generate_ordinates", "ordinate_count",
@@ -31,6 +31,7 @@ ROM_E_ARG, ROM_E_DOMAIN, ROM_E_STATE, ROM_E_NOMEM, ROM_E_DEVICE, ROM_E_DIVERGED,
     -1, -2, -3, -4, -5, -6, -7
 ROM_SCHEME_STEP, ROM_SCHEME_DD = 0, 1
 ROM_SCAT_ISO, ROM_SCAT_LINEAR, ROM_SCAT_HG, ROM_SCAT_DENSE = 0, 1, 2, 3
+ROM_SCAT_NORMALIZE = 0x10  # flag OR-ed into a kernel kind: rows of P rescaled to unit weighted sum
 ROM_ORD_STRATIFIED, ROM_ORD_IID_SPHERE, ROM_ORD_UNIFORM2D, ROM_ORD_GAUSS2D = 0, 1, 2, 3
 ROM_PREC_FP32, ROM_PREC_FP64 = 0, 1
 ROM_SWEEP_AUTO, ROM_SWEEP_STRIP, ROM_SWEEP_DIAG = 0, 1, 2
