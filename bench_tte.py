@@ -26,7 +26,11 @@ Problems (vacuum, unit square):
   iso64   -- 64 x 64,  sigma_t = 1, sigma_s = 0.5, isotropic, q = 1 on [0.45, 0.55)^2
   iso512  -- 512 x 512, sigma_t = 1, sigma_s = 0.5, isotropic, q = 1 on [0.49, 0.51)^2
   aniso64 -- 64 x 64,  sigma_t = 1, sigma_s = 0.8, Henyey-Greenstein g = 0.8 folded over the
-             polar sign, q = 1 on [0.45, 0.55)^2
+             polar sign and row-normalized (every arm, the reference included), q = 1 on
+             [0.45, 0.55)^2; the raw kernel makes some small random samples diverge
+  aniso64raw -- the same with the raw (unnormalized) kernel
+  aniso256 -- aniso64 on 256 x 256 cells, q = 1 on [0.45, 0.55)^2
+  lin64   -- iso64 with the paper's linear kernel 1 + g cos(xi), g = 0.9 (eq. (2.1)), raw
 
 Usage: python bench_tte.py --problem iso64 [--out FILE]; one JSON line per measurement on
 stdout (flushed as it is taken), then a summary line.
@@ -47,7 +51,10 @@ import rom_inputs as RI
 PROBLEMS = {
     "iso64": dict(nx=64, sigma_s=0.5, lo=0.45, hi=0.55, scat="iso", g=0.0, ref_n=200),
     "iso512": dict(nx=512, sigma_s=0.5, lo=0.49, hi=0.51, scat="iso", g=0.0, ref_n=200),
-    "aniso64": dict(nx=64, sigma_s=0.8, lo=0.45, hi=0.55, scat="hg", g=0.8, ref_n=80),
+    "aniso64": dict(nx=64, sigma_s=0.8, lo=0.45, hi=0.55, scat="hg", g=0.8, ref_n=80, norm=True),
+    "aniso64raw": dict(nx=64, sigma_s=0.8, lo=0.45, hi=0.55, scat="hg", g=0.8, ref_n=80),
+    "aniso256": dict(nx=256, sigma_s=0.8, lo=0.45, hi=0.55, scat="hg", g=0.8, ref_n=80, norm=True),
+    "lin64": dict(nx=64, sigma_s=0.5, lo=0.45, hi=0.55, scat="linear", g=0.9, ref_n=200),
 }
 
 
@@ -81,8 +88,9 @@ class Runner:
         f = RI.uniform_fields(p["nx"], p["nx"], 1.0, p["sigma_s"], p["lo"], p["hi"])
         self.f = f
         self.h = R.Handle(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
-        if p["scat"] == "hg":
-            self.h.set_scattering(R.ROM_SCAT_HG, p["g"])
+        if p["scat"] != "iso":
+            kind = R.ROM_SCAT_HG if p["scat"] == "hg" else R.ROM_SCAT_LINEAR
+            self.h.set_scattering(kind | (R.ROM_SCAT_NORMALIZE if p.get("norm") else 0), p["g"])
         self.outf = open(a.out, "a") if a.out else None
 
     def emit(self, rec):
