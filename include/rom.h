@@ -211,6 +211,15 @@ int rom_source_iterate(rom_handle* h, const rom_si_opts* opts, double* phi, rom_
 int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* spec,
                  const rom_si_opts* opts, double* mean, double* var, rom_ens_stats* stats);
 
+/* The samples first .. first + t - 1 of the same ensemble (Sec. 4.1): generated and solved as
+ * rom_ensemble does, but each sample's scalar flux is returned, phis [t][cells] (sample-major,
+ * host FP64), instead of the moments.  For statistics that the mean and variance do not give, such
+ * as the expected per-sample error E||phi^xi - phi_ref|| or the Monte Carlo error of a running
+ * average (both defined in Sec. 4.1); first >= 0 lets a large ensemble be taken in pieces.
+ * Errors as rom_ensemble; the handle keeps no device result (rom_phi_device fails after it). */
+int rom_ensemble_samples(rom_handle* h, int32_t t, uint64_t seed, int64_t first, const rom_ord_spec* spec,
+                         const rom_si_opts* opts, double* phis, rom_ens_stats* stats);
+
 /* k independent problems solved together in one persistent sweep launch per iteration; each
  * handle must have ordinates set; phis[i] [cells_i] receives handle i's scalar flux (entries may
  * be NULL); stats (optional) is [k].  All handles must use the same stream and device. */

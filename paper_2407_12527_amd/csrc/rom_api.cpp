@@ -11,6 +11,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <memory>
 #include <string>
@@ -1724,6 +1725,98 @@ int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opt
     return ROM_OK;
 }
 
+// Running statistics of an ensemble's batches.
+struct EnsAgg {
+    int min_it = 1 << 30, max_it = 0, worst = ROM_OK, sweeps = 0;
+    int64_t updates = 0;
+    double ms = 0, sweep_ms = 0;
+    int shape[5] = {0, 0, 0, 0, 0};
+
+    void fill(rom_ens_stats* st, int t) const
+    {
+        if (!st) return;
+        st->samples = t;
+        st->min_iters = min_it;
+        st->max_iters = max_it;
+        st->status = worst == ROM_OK ? ROM_OK : ROM_NOT_CONVERGED;
+        st->updates = updates;
+        st->device_ms = ms;
+        st->sweep_ms = sweep_ms;
+        st->sweeps = sweeps;
+        st->tile_x = shape[0];
+        st->tile_y = shape[1];
+        st->band = shape[2];
+        st->lanes = shape[3];
+        st->sweep = shape[4];
+    }
+};
+
+int check_ensemble(rom_handle* h, const rom_ord_spec& spec, const rom_si_opts* opts, rom_si_opts& o)
+{
+    if (ordinate_count(spec) <= 0) return fail(h, ROM_E_ARG, "bad ordinate spec");
+    if (h->scat == ROM_SCAT_DENSE) return fail(h, ROM_E_STATE, "a dense kernel belongs to one ordinate set");
+    return validate_opts(h, opts, o);
+}
+
+// Samples first .. first + t - 1 of (spec, seed), generated exactly as rom_generate_ordinates
+// does, solved in batches (as many samples per launch as a 24 GiB budget and 1024 allow) with
+// one cached plan per batch shape, refreshed with each batch's ordinates.  After each batch,
+// per_batch(plan, index of the batch's first sample in this call, batch size) consumes the
+// fluxes while they are on the device.
+int ensemble_batches(rom_handle* h, int64_t first, int t, uint64_t seed, const rom_ord_spec& spec, const rom_si_opts& o,
+                     const std::function<void(Plan&, int, int)>& per_batch, EnsAgg& ag)
+{
+    const int n = ordinate_count(spec);
+    const bool aniso = is_aniso(h);
+    const int64_t per_sample = h->cells * (int64_t)(aniso ? (n + 128) * 6 : 0) + h->cells * 8 * 8 +
+                               (int64_t)h->grid.nx * h->grid.ny / 2 * 4;
+    const int64_t budget = (int64_t)24 << 30;
+    int B = (int)std::max<int64_t>(1, std::min<int64_t>(t, budget / std::max<int64_t>(per_sample, 1)));
+    B = std::min(B, 1024);
+    std::vector<double> dirs((size_t)t * 3 * n), w((size_t)t * n);
+    for (int smp = 0; smp < t; ++smp) {
+        const int rc = generate_ordinates(spec, seed, first + smp, dirs.data() + (size_t)smp * 3 * n, w.data() + (size_t)smp * n);
+        if (rc) return fail(h, rc, "ordinate generation failed");
+    }
+    std::unique_ptr<Plan>& P = h->ens_plan;
+    int done = 0;
+    while (done < t) {
+        const int b = std::min(B, t - done);
+        std::vector<SysInput> in;
+        for (int k = 0; k < b; ++k)
+            in.push_back({h, dirs.data() + (size_t)(done + k) * 3 * n, w.data() + (size_t)(done + k) * n, n, false});
+        char kb[96];
+        std::snprintf(kb, sizeof kb, " e%d %d %d %d", spec.kind, n, b, h->scat);
+        const std::string key = plan_signature(o, scat_sig(h), 2, b) + kb;
+        const int reuse = (P && h->ens_key == key) ? 2 : 0;
+        if (!reuse) P.reset();
+        h->ens_key.clear();
+        SolveResult res;
+        const int rc = solve_systems(h, in, o, reuse, P, res);
+        if (rc) return rc;
+        h->ens_key = key;
+        ag.ms += res.ms;
+        ag.sweep_ms += res.sweep_ms;
+        ag.sweeps += res.sweeps;
+        ag.shape[0] = res.tx;
+        ag.shape[1] = res.ty;
+        ag.shape[2] = res.band;
+        ag.shape[3] = res.lanes;
+        ag.shape[4] = res.kind;
+        for (int k = 0; k < b; ++k) {
+            const SysCtl& sc = res.sc[k];
+            ag.min_it = std::min(ag.min_it, sc.iter);
+            ag.max_it = std::max(ag.max_it, sc.iter);
+            ag.updates += (int64_t)sc.iter * h->cells * n;
+            if (sc.state == 3) ag.worst = ROM_E_DIVERGED;
+            else if (sc.state != 1 && ag.worst == ROM_OK) ag.worst = ROM_NOT_CONVERGED;
+        }
+        per_batch(*P, done, b);
+        done += b;
+    }
+    return ROM_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -1845,105 +1938,69 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
 {
     if (!h) return ROM_E_ARG;
     if (t <= 0 || !spec) return fail(h, ROM_E_ARG, "t must be > 0 and spec non-NULL");
-    const int n = ordinate_count(*spec);
-    if (n <= 0) return fail(h, ROM_E_ARG, "bad ordinate spec");
-    if (h->scat == ROM_SCAT_DENSE) return fail(h, ROM_E_STATE, "a dense kernel belongs to one ordinate set");
     rom_si_opts o;
-    int rc = validate_opts(h, opts, o);
+    int rc = check_ensemble(h, *spec, opts, o);
     if (rc) return rc;
     try {
         hipStream_t s = h->stream();
         HIPCHK(h->ens_mean.alloc(h->cells * 8));
         HIPCHK(h->ens_m2.alloc(h->cells * 8));
         HIPCHK(h->ens_var.alloc(h->cells * 8));
-        // batch size: bounded by a device-memory budget for the per-sample buffers
-        const bool aniso = is_aniso(h);
-        const int64_t per_sample = h->cells * (int64_t)(aniso ? (n + 128) * 6 : 0) + h->cells * 8 * 8 +
-                                   (int64_t)h->grid.nx * h->grid.ny / 2 * 4;
-        const int64_t budget = (int64_t)24 << 30;
-        int B = (int)std::max<int64_t>(1, std::min<int64_t>(t, budget / std::max<int64_t>(per_sample, 1)));
-        B = std::min(B, 1024);
-        std::vector<double> dirs((size_t)t * 3 * n), w((size_t)t * n);
-        for (int smp = 0; smp < t; ++smp) {
-            rc = generate_ordinates(*spec, seed, smp, dirs.data() + (size_t)smp * 3 * n, w.data() + (size_t)smp * n);
-            if (rc) return fail(h, rc, "ordinate generation failed");
-        }
-        int done = 0, min_it = 1 << 30, max_it = 0, worst = ROM_OK, sweeps = 0;
-        int64_t updates = 0;
-        double ms = 0, sweep_ms = 0;
-        int shape[5] = {0, 0, 0, 0, 0};
-        // one plan per batch shape, refreshed with each batch's ordinates
-        std::unique_ptr<Plan>& P = h->ens_plan;
         std::vector<int64_t> offs;
         DevMem d_offs;
-        while (done < t) {
-            const int b = std::min(B, t - done);
-            std::vector<SysInput> in;
-            for (int k = 0; k < b; ++k)
-                in.push_back({h, dirs.data() + (size_t)(done + k) * 3 * n, w.data() + (size_t)(done + k) * n, n, false});
-            char kb[96];
-            std::snprintf(kb, sizeof kb, " e%d %d %d %d", spec->kind, n, b, h->scat);
-            const std::string key = plan_signature(o, scat_sig(h), 2, b) + kb;
-            const int reuse = (P && h->ens_key == key) ? 2 : 0;
-            if (!reuse) P.reset();
-            h->ens_key.clear();
-            SolveResult res;
-            rc = solve_systems(h, in, o, reuse, P, res);
-            if (rc) return rc;
-            h->ens_key = key;
-            ms += res.ms;
-            sweep_ms += res.sweep_ms;
-            sweeps += res.sweeps;
-            shape[0] = res.tx;
-            shape[1] = res.ty;
-            shape[2] = res.band;
-            shape[3] = res.lanes;
-            shape[4] = res.kind;
+        EnsAgg ag;
+        // FP64 moments of each batch, merged into the running ones (eq. (4.6))
+        auto moments = [&](Plan& P, int done, int b) {
             offs.assign(b, 0);
-            for (int k = 0; k < b; ++k) {
-                offs[k] = P->sys[k].phi_off;
-                const SysCtl& sc = res.sc[k];
-                min_it = std::min(min_it, sc.iter);
-                max_it = std::max(max_it, sc.iter);
-                updates += (int64_t)sc.iter * h->cells * n;
-                if (sc.state == 3) worst = ROM_E_DIVERGED;
-                else if (sc.state != 1 && worst == ROM_OK) worst = ROM_NOT_CONVERGED;
-            }
+            for (int k = 0; k < b; ++k) offs[k] = P.sys[k].phi_off;
             upload(d_offs, offs);
             MomentsArgs ma{};
-            ma.phi = P->d_phi.p;
+            ma.phi = P.d_phi.p;
             ma.phi_offs = d_offs.as<int64_t>();
             ma.t = b;
             ma.count = done;
             ma.cells = h->cells;
             ma.mean = h->ens_mean.as<double>();
             ma.m2 = h->ens_m2.as<double>();
-            HIPCHK(launch_moments(ma, P->fp64, s));
-            done += b;
-        }
+            HIPCHK(launch_moments(ma, P.fp64, s));
+        };
+        rc = ensemble_batches(h, 0, t, seed, *spec, o, moments, ag);
+        if (rc) return rc;
         HIPCHK(launch_finish_var(h->ens_m2.as<double>(), h->ens_var.as<double>(), h->cells, t, s));
         HIPCHK(hipStreamSynchronize(s));
         if (mean) HIPCHK(hipMemcpy(mean, h->ens_mean.p, h->cells * 8, hipMemcpyDeviceToHost));
         if (var) HIPCHK(hipMemcpy(var, h->ens_var.p, h->cells * 8, hipMemcpyDeviceToHost));
         h->res_dev = h->ens_mean.p;
         h->res_fp64 = true;
-        if (stats) {
-            stats->samples = t;
-            stats->min_iters = min_it;
-            stats->max_iters = max_it;
-            stats->status = worst == ROM_OK ? ROM_OK : ROM_NOT_CONVERGED;
-            stats->updates = updates;
-            stats->device_ms = ms;
-            stats->sweep_ms = sweep_ms;
-            stats->sweeps = sweeps;
-            stats->tile_x = shape[0];
-            stats->tile_y = shape[1];
-            stats->band = shape[2];
-            stats->lanes = shape[3];
-            stats->sweep = shape[4];
-        }
-        if (worst == ROM_E_DIVERGED) return fail(h, ROM_E_DIVERGED, "non-finite iterate in a sample");
-        return worst;
+        ag.fill(stats, t);
+        if (ag.worst == ROM_E_DIVERGED) return fail(h, ROM_E_DIVERGED, "non-finite iterate in a sample");
+        return ag.worst;
+    } catch (const Fail& f) {
+        return fail(h, f.code, f.msg);
+    } catch (const std::bad_alloc&) {
+        return fail(h, ROM_E_NOMEM, "host allocation failed");
+    }
+}
+
+int rom_ensemble_samples(rom_handle* h, int32_t t, uint64_t seed, int64_t first, const rom_ord_spec* spec,
+                         const rom_si_opts* opts, double* phis, rom_ens_stats* stats)
+{
+    if (!h) return ROM_E_ARG;
+    if (t <= 0 || !spec || !phis || first < 0) return fail(h, ROM_E_ARG, "t > 0, first >= 0, spec and phis non-NULL");
+    rom_si_opts o;
+    int rc = check_ensemble(h, *spec, opts, o);
+    if (rc) return rc;
+    try {
+        EnsAgg ag;
+        auto download = [&](Plan& P, int done, int b) {
+            for (int k = 0; k < b; ++k) download_phi(P, k, phis + (size_t)(done + k) * h->cells);
+        };
+        rc = ensemble_batches(h, first, t, seed, *spec, o, download, ag);
+        if (rc) return rc;
+        h->res_dev = nullptr;
+        ag.fill(stats, t);
+        if (ag.worst == ROM_E_DIVERGED) return fail(h, ROM_E_DIVERGED, "non-finite iterate in a sample");
+        return ag.worst;
     } catch (const Fail& f) {
         return fail(h, f.code, f.msg);
     } catch (const std::bad_alloc&) {

@@ -22,7 +22,7 @@ __all__ = [
     "RomError", "Handle", "lib", "library_path", "EXPORTS", "generate_ordinates", "ordinate_count",
     "solve_batch", "si_opts", "rom_create", "rom_destroy", "rom_set_stream", "rom_set_ordinates",
     "rom_set_inflow_angular", "rom_set_scattering", "rom_sweep", "rom_source_iterate", "rom_ensemble",
-    "rom_solve_batch", "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
+    "rom_ensemble_samples", "rom_solve_batch", "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
     "rom_last_error", "rom_version",
 ]
 
@@ -39,7 +39,8 @@ ROM_FACE_LEFT, ROM_FACE_RIGHT, ROM_FACE_BOTTOM, ROM_FACE_TOP = 0, 1, 2, 3
 
 # every function declared in include/rom.h
 EXPORTS = ("rom_create", "rom_destroy", "rom_set_stream", "rom_set_ordinates", "rom_set_inflow_angular",
-           "rom_set_scattering", "rom_sweep", "rom_source_iterate", "rom_ensemble", "rom_solve_batch",
+           "rom_set_scattering", "rom_sweep", "rom_source_iterate", "rom_ensemble", "rom_ensemble_samples",
+           "rom_solve_batch",
            "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
            "rom_last_error", "rom_version")
 
@@ -110,6 +111,8 @@ def lib():
         L.rom_source_iterate.argtypes = [P, C.POINTER(rom_si_opts), P, C.POINTER(rom_si_stats)]
         L.rom_ensemble.argtypes = [P, C.c_int32, C.c_uint64, C.POINTER(rom_ord_spec), C.POINTER(rom_si_opts), P, P,
                                    C.POINTER(rom_ens_stats)]
+        L.rom_ensemble_samples.argtypes = [P, C.c_int32, C.c_uint64, C.c_int64, C.POINTER(rom_ord_spec),
+                                           C.POINTER(rom_si_opts), P, C.POINTER(rom_ens_stats)]
         L.rom_solve_batch.argtypes = [C.POINTER(C.c_void_p), C.c_int32, C.POINTER(rom_si_opts),
                                       C.POINTER(C.c_void_p), C.POINTER(rom_si_stats)]
         L.rom_phi_device.argtypes = [P, C.POINTER(C.c_void_p), C.POINTER(C.c_int32)]
@@ -160,6 +163,10 @@ def rom_source_iterate(h, opts, phi, stats):
 
 def rom_ensemble(h, t, seed, spec, opts, mean, var, stats):
     return lib().rom_ensemble(h, t, seed, spec, opts, mean, var, stats)
+
+
+def rom_ensemble_samples(h, t, seed, first, spec, opts, phis, stats):
+    return lib().rom_ensemble_samples(h, t, seed, first, spec, opts, phis, stats)
 
 
 def rom_solve_batch(hs, k, opts, phis, stats):
@@ -325,6 +332,15 @@ class Handle:
         rc = _check(lib().rom_ensemble(self.h, t, seed, C.byref(spec), C.byref(opts) if opts else None, _ptr(mean),
                                        _ptr(var), C.byref(st)), self.h)
         return mean, var, st, rc
+
+    def ensemble_samples(self, t, seed, kind, p1, p2=0, first=0, opts=None):
+        """Scalar fluxes [t, cells] of samples first .. first + t - 1 of the ensemble (seed, spec)."""
+        phis = np.empty((t, self.cells))
+        st = rom_ens_stats()
+        spec = rom_ord_spec(kind, p1, p2)
+        rc = _check(lib().rom_ensemble_samples(self.h, t, seed, first, C.byref(spec), C.byref(opts) if opts else None,
+                                               _ptr(phis), C.byref(st)), self.h)
+        return phis, st, rc
 
     def phi_device(self):
         dev = C.c_void_p()
