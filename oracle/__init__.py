@@ -77,6 +77,11 @@ def lib():
         L.orc_ensemble.argtypes = [C.POINTER(Grid), P, P, P, C.POINTER(Inflow), C.c_int, C.c_int, C.c_int,
                                    C.c_uint64, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int, C.c_double,
                                    C.c_int, P, P, P, P]
+        L.orc_slab_ordinates_rom.argtypes = [C.c_int, C.c_uint64, C.c_int64, P, P]
+        L.orc_slab_quadrature.argtypes = [C.c_int, C.c_int, P, P]
+        L.orc_slab_sweep.argtypes = [C.c_int, C.c_double, C.c_double, P, C.c_int, P, P, P, P]
+        L.orc_slab_source_iterate.argtypes = [C.c_int, C.c_double, C.c_double, P, P, P, C.c_int, P, P, P,
+                                              C.c_double, C.c_int, P, C.POINTER(C.c_int), C.POINTER(C.c_double)]
         L.orc_num_threads.restype = C.c_int
         L.orc_set_num_threads.argtypes = [C.c_int]
         _lib = L
@@ -271,3 +276,50 @@ def ensemble(prob: Problem, ord_kind, p1, p2, seed, t, scat_kind=SCAT_ISO, g=0.0
     if want_phis:
         out["phis"] = phis
     return out
+
+
+# ------------------------------------------------------------------ slab geometry (Sec. 4.1)
+SLAB_GAUSS, SLAB_UNIFORM = 0, 1
+
+
+def slab_rom_ordinates(n: int, seed: int = 0, sample: int = 0):
+    """ROM slab ordinates (Sec. 4.1): one uniform draw in each of the n/2 cells of [-1, 0],
+    mirrored into [0, 1]; weights 1/n (sum 1)."""
+    mu = np.empty(n)
+    w = np.empty(n)
+    if lib().orc_slab_ordinates_rom(n, seed, sample, _p(mu), _p(w)) != 0:
+        raise ValueError("orc_slab_ordinates_rom failed")
+    return mu, w
+
+
+def slab_quadrature(kind: int, n: int):
+    """DOM slab quadrature: SLAB_GAUSS (Gauss-Legendre) or SLAB_UNIFORM (midpoints); weights sum 1."""
+    mu = np.empty(n)
+    w = np.empty(n)
+    if lib().orc_slab_quadrature(kind, n, _p(mu), _p(w)) != 0:
+        raise ValueError("orc_slab_quadrature failed")
+    return mu, w
+
+
+def slab_sweep(nx, x0, x1, sigma_t, mu, inflow, S):
+    """psi [n, nx+1] for node sources S [nx+1] (diamond difference at the grid points)."""
+    mu = _f64(mu)
+    psi = np.empty((mu.size, nx + 1))
+    rc = lib().orc_slab_sweep(nx, x0, x1, _p(_f64(sigma_t)), mu.size, _p(mu), _p(_f64(inflow)), _p(_f64(S)), _p(psi))
+    if rc != 0:
+        raise ValueError(f"orc_slab_sweep failed ({rc})")
+    return psi
+
+
+def slab_source_iterate(nx, x0, x1, sigma_t, sigma_s, q, mu, w, inflow, tol=1e-10, max_iter=10000):
+    """Slab source iteration from phi^0 = 0; fields at the nx + 1 grid points."""
+    mu = _f64(mu)
+    phi = np.empty(nx + 1)
+    it = C.c_int(0)
+    r = C.c_double(0.0)
+    rc = lib().orc_slab_source_iterate(nx, x0, x1, _p(_f64(sigma_t)), _p(_f64(sigma_s)), _p(_f64(q)), mu.size,
+                                       _p(mu), _p(_f64(w)), _p(_f64(inflow)), tol, max_iter, _p(phi),
+                                       C.byref(it), C.byref(r))
+    if rc < 0:
+        raise ValueError(f"orc_slab_source_iterate failed ({rc})")
+    return {"phi": phi, "iters": it.value, "r": r.value, "status": rc}

@@ -605,3 +605,131 @@ int orc_ensemble(const orc_grid *g, const double *sigma_t, const double *sigma_s
     if (!phis) free(all);
     return status;
 }
+
+/* ------------------------------------------------------------------------------------------ */
+/* Slab geometry (Sec. 4.1, Example 4.1): mu psi_x + sigma_t psi = sigma_s phi + q on [x0, x1], */
+/* phi = (1/2) int psi dmu, isotropic scattering P = 1.                                         */
+/*                                                                                            */
+/* Readings (the paper's second-order scheme [ShiA] is not given in its text): unknowns at the */
+/* grid points x_i = x0 + i dx, i = 0..nx, as the paper's slab error norm uses; diamond        */
+/* difference on each cell [x_i, x_{i+1}] with the cell's sigma_t the mean of its end values    */
+/* and the cell source the mean of its end sources,                                            */
+/*   |mu| (psi_out - psi_in) / dx + sigma_c (psi_in + psi_out) / 2 = (S_i + S_{i+1}) / 2;       */
+/* weights normalized to sum 1 (the paper's 2/n together with the 1/2 of the slab average), so */
+/* phi = sum_l w_l psi_l.                                                                      */
+/* ------------------------------------------------------------------------------------------ */
+
+/* ROM slab ordinates: [-1, 1] cut into n equal cells (n even); one uniform draw in each cell of
+ * [-1, 0], the cells of [0, 1] get the mirror images mu_l = -mu_{n+1-l}; weights 1/n.  The
+ * draws use sample `sample`'s SplitMix64 stream, cells in increasing order. */
+int orc_slab_ordinates_rom(int n, uint64_t seed, int64_t sample, double *mu, double *w)
+{
+    if (n <= 0 || (n & 1) || !mu || !w) return ORC_EARG;
+    uint64_t st = orc_sample_seed(seed, sample);
+    const int m = n / 2;
+    const double width = 2.0 / (double)n;
+    for (int l = 0; l < m; ++l) {
+        const double u = orc_u01(orc_splitmix64_next(&st));
+        mu[l] = -1.0 + (double)l * width + u * width;  /* cell l of [-1, 0], counted from -1 */
+    }
+    for (int l = m; l < n; ++l) mu[l] = -mu[n - 1 - l];
+    for (int l = 0; l < n; ++l) w[l] = 1.0 / (double)n;
+    return ORC_OK;
+}
+
+/* DOM slab quadratures: kind 0 Gauss-Legendre on [-1, 1] (weights halved), kind 1 the uniform
+ * midpoint rule of n equal cells. */
+int orc_slab_quadrature(int kind, int n, double *mu, double *w)
+{
+    if (n <= 0 || !mu || !w) return ORC_EARG;
+    if (kind == 0) {
+        int rc = orc_gauss_legendre(n, mu, w);
+        if (rc) return rc;
+        for (int l = 0; l < n; ++l) w[l] *= 0.5;
+        return ORC_OK;
+    }
+    if (kind == 1) {
+        for (int l = 0; l < n; ++l) {
+            mu[l] = -1.0 + (2.0 * l + 1.0) / (double)n;
+            w[l] = 1.0 / (double)n;
+        }
+        return ORC_OK;
+    }
+    return ORC_EARG;
+}
+
+/* One slab sweep of every ordinate for the node source S [nx+1]: psi [n][nx+1].  inflow[l] is
+ * psi at the entry boundary of ordinate l (x0 when mu_l > 0, x1 when mu_l < 0). */
+int orc_slab_sweep(int nx, double x0, double x1, const double *sigma_t, int n, const double *mu,
+                   const double *inflow, const double *S, double *psi)
+{
+    if (nx <= 0 || !(x1 > x0) || !sigma_t || n <= 0 || !mu || !inflow || !S || !psi) return ORC_EARG;
+    const double dx = (x1 - x0) / (double)nx;
+    for (int l = 0; l < n; ++l) {
+        if (mu[l] == 0.0) return ORC_EARG;
+        const double a = fabs(mu[l]) / dx;
+        double *p = psi + (size_t)l * (nx + 1);
+        if (mu[l] > 0.0) {
+            p[0] = inflow[l];
+            for (int i = 0; i < nx; ++i) {
+                const double sc = 0.5 * (sigma_t[i] + sigma_t[i + 1]);
+                const double sbar = 0.5 * (S[i] + S[i + 1]);
+                p[i + 1] = ((a - 0.5 * sc) * p[i] + sbar) / (a + 0.5 * sc);
+            }
+        } else {
+            p[nx] = inflow[l];
+            for (int i = nx - 1; i >= 0; --i) {
+                const double sc = 0.5 * (sigma_t[i] + sigma_t[i + 1]);
+                const double sbar = 0.5 * (S[i] + S[i + 1]);
+                p[i] = ((a - 0.5 * sc) * p[i + 1] + sbar) / (a + 0.5 * sc);
+            }
+        }
+    }
+    return ORC_OK;
+}
+
+/* Slab source iteration from phi^0 = 0 with the same stopping rule as the X-Y case. */
+int orc_slab_source_iterate(int nx, double x0, double x1, const double *sigma_t, const double *sigma_s,
+                            const double *q, int n, const double *mu, const double *w, const double *inflow,
+                            double tol, int max_iter, double *phi, int *iters, double *final_r)
+{
+    if (nx <= 0 || !sigma_s || !q || !w || !phi || max_iter <= 0) return ORC_EARG;
+    const size_t nn = (size_t)nx + 1;
+    double *psi = (double *)malloc(sizeof(double) * (size_t)n * nn);
+    double *S = (double *)malloc(sizeof(double) * nn);
+    double *old = (double *)malloc(sizeof(double) * nn);
+    if (!psi || !S || !old) {
+        free(psi);
+        free(S);
+        free(old);
+        return ORC_ENOMEM;
+    }
+    for (size_t i = 0; i < nn; ++i) phi[i] = 0.0;
+    int status = ORC_NOT_CONVERGED, k;
+    double r = 0.0;
+    for (k = 1; k <= max_iter; ++k) {
+        for (size_t i = 0; i < nn; ++i) S[i] = sigma_s[i] * phi[i] + q[i];
+        memcpy(old, phi, sizeof(double) * nn);
+        int rc = orc_slab_sweep(nx, x0, x1, sigma_t, n, mu, inflow, S, psi);
+        if (rc) {
+            status = rc;
+            break;
+        }
+        for (size_t i = 0; i < nn; ++i) {
+            double acc = 0.0;
+            for (int l = 0; l < n; ++l) acc += w[l] * psi[(size_t)l * nn + i];
+            phi[i] = acc;
+        }
+        r = rel_change(nn, phi, old);
+        if (r <= tol) {
+            status = ORC_OK;
+            break;
+        }
+    }
+    if (iters) *iters = (k <= max_iter) ? k : max_iter;
+    if (final_r) *final_r = r;
+    free(psi);
+    free(S);
+    free(old);
+    return status;
+}

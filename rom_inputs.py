@@ -163,4 +163,35 @@ def example21(n=100) -> Fields:
     return uniform_fields(n, n, 1.0, 0.5, 0.4, 0.6, q_val=2.0)
 
 
+@dataclass
+class SlabFields:
+    """Slab problem on [x0, x1] with nx cells; fields at the nx + 1 grid points x_i = x0 + i dx,
+    and the boundary inflow as a function of mu (left face for mu > 0, right face for mu < 0)."""
+    nx: int
+    sigma_t: np.ndarray
+    sigma_s: np.ndarray
+    q: np.ndarray
+    inflow: object
+    x0: float = 0.0
+    x1: float = 1.0
+
+
+def slab_example41(nx=50, case=1) -> SlabFields:
+    """Example 4.1 (Sec. 4.1): sigma_t = 10x^2 + 1, sigma_s = 5x^2 + 0.5, q = 1 + x on [0, 1], with
+    the inflow of case 1 (smooth), 2 (continuous, not differentiable) or 3 (discontinuous)."""
+    x = np.linspace(0.0, 1.0, nx + 1)
+
+    def inflow(mu):
+        mu = np.asarray(mu, dtype=float)
+        if case == 1:
+            return np.where(mu > 0, 3 * mu, -5 * mu)
+        if case not in (2, 3):
+            raise ValueError("case must be 1, 2 or 3")
+        left = np.where(mu > 1 / 3, (4 / 3 if case == 2 else 3) - mu, 3 * mu)
+        right = np.where(mu < -1 / 3, (2 if case == 2 else 4) + mu, -5 * mu)
+        return np.where(mu > 0, left, right)
+
+    return SlabFields(nx, 10 * x * x + 1, 5 * x * x + 0.5, 1 + x, inflow)
+
+
 WORKLOADS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c5": c5}
