@@ -40,9 +40,9 @@ KERNEL_SOURCES = {
               "rom_sweep_f32_8x4.hip", "rom_sweep_f32_8x8.hip", "rom_sweep_f64.hip"],
 }
 MEASURED_TRAFFIC = {  # workload: (kernel family, shape as in config, source hash, bytes per launch)
-    "c2": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "3de2ae3256e51ccb", 38485175),
-    "c1": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 1}, "3de2ae3256e51ccb", 1788459),
-    "c3": ("strip", {"sweep_tile": "16x16", "band": 4}, "1aa59c6eb0beb8a8", 934037490),
+    "c2": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "8c9c77a7a2842fc1", 38476813),
+    "c1": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 1}, "8c9c77a7a2842fc1", 1809342),
+    "c3": ("strip", {"sweep_tile": "16x16", "band": 4}, "6c2c5693091b649e", 935117138),
 }
 
 
