@@ -231,6 +231,46 @@ int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, d
  * For rom_ensemble this is the FP64 mean. */
 int rom_phi_device(const rom_handle* h, const void** dev, int32_t* is_fp64);
 
+/* ---- slab geometry (Sec. 4.1) ----------------------------------------------------------------
+ * mu dpsi/dx + sigma_t psi = sigma_s phi + q on [x0, x1], phi = (1/2) int_{-1}^{1} psi dmu,
+ * isotropic scattering, inflow psi(x0, mu > 0) and psi(x1, mu < 0) (Example 4.1).  Unknowns at
+ * the nx + 1 grid points x_i = x0 + i (x1 - x0) / nx (the paper's slab error norm is over them);
+ * each cell [x_i, x_{i+1}] is closed by diamond difference with the cell's sigma_t and source the
+ * means of its end values:
+ *   |mu| (psi_out - psi_in) / dx + sigma_c (psi_in + psi_out) / 2 = (S_i + S_{i+1}) / 2,
+ * S_i = sigma_s(x_i) phi_i + q(x_i) (a second-order scheme; the paper's own [ShiA] scheme is not
+ * given in its text).  Weights sum to 1: phi_i = sum_l w_l psi_l(x_i). */
+typedef struct rom_slab rom_slab;
+
+#define ROM_SLAB_RANDOM 0  /* ROM: one draw per cell of [-1, 0] (n even), mirrored; w = 1/n */
+#define ROM_SLAB_GAUSS 1   /* Gauss-Legendre on [-1, 1], weights halved */
+#define ROM_SLAB_UNIFORM 2 /* midpoints of n equal cells, w = 1/n */
+
+/* A slab problem: sigma_t, sigma_s, q [nx + 1] at the grid points (host FP64, copied), with
+ * sigma_t > 0, 0 <= sigma_s < sigma_t, q >= 0, all finite; nx >= 1, x1 > x0. */
+int rom_slab_create(int32_t nx, double x0, double x1, const double* sigma_t, const double* sigma_s,
+                    const double* q, rom_slab** out);
+void rom_slab_destroy(rom_slab* s);
+/* Queue the slab's device work on this HIP stream (NULL: the slab's own stream). */
+int rom_slab_set_stream(rom_slab* s, void* hip_stream);
+
+/* t independent slab systems, system k with the n ordinates mu [k][n] (0 < |mu| <= 1), weights
+ * w [k][n] (> 0, summing to 1 within 1e-12) and entry-face inflow [k][n] (finite, >= 0), each
+ * solved by source iteration from phi = 0 to opts->tol (relative max-norm change, as
+ * rom_source_iterate) on the GPU, one wavefront per 64 / L systems (L lanes per system, each
+ * lane carrying up to 64 ordinates; n <= 4096).  phis [t][nx + 1] receives every system's
+ * scalar flux (host FP64); iters [t] (optional) the iterations each took.  opts->precision
+ * selects FP32 or FP64 arithmetic; tile, band and sweep options are ignored.  Returns
+ * ROM_NOT_CONVERGED if a system reached max_iter, ROM_E_DIVERGED if one became non-finite. */
+int rom_slab_solve(rom_slab* s, int32_t t, int32_t n, const double* mu, const double* w, const double* inflow,
+                   const rom_si_opts* opts, double* phis, int32_t* iters, rom_ens_stats* stats);
+
+/* Slab ordinate set (host only): kind ROM_SLAB_RANDOM (sample `sample` of `seed`, same
+ * SplitMix64 streams as rom_generate_ordinates), ROM_SLAB_GAUSS or ROM_SLAB_UNIFORM; mu [n], w [n]. */
+int rom_slab_ordinates(int32_t kind, int32_t n, uint64_t seed, int64_t sample, double* mu, double* w);
+
+const char* rom_slab_last_error(const rom_slab* s);
+
 /* ---- host utilities (no device work) ------------------------------------------------------ */
 
 /* Ordinate set of sample `sample` for the recipe (Sec. 3.1 steps 1-2, Sec. 4.2; Appendix A for

@@ -322,6 +322,26 @@ struct Plan {
     }
 };
 
+// Slab-geometry problem (Sec. 4.1): fields at the nx + 1 grid points, host copies.
+struct rom_slab {
+    int32_t nx = 0;
+    double x0 = 0, x1 = 1;
+    std::vector<double> st, ss, q;
+    hipStream_t user_stream = nullptr;
+    hipStream_t own_stream = nullptr;
+    std::string err;
+    hipStream_t stream()
+    {
+        if (user_stream) return user_stream;
+        if (!own_stream) HIPCHK(hipStreamCreateWithFlags(&own_stream, hipStreamNonBlocking));
+        return own_stream;
+    }
+    ~rom_slab()
+    {
+        if (own_stream) (void)hipStreamDestroy(own_stream);
+    }
+};
+
 rom_handle::~rom_handle()
 {
     plan.reset();
@@ -2007,5 +2027,195 @@ int rom_ensemble_samples(rom_handle* h, int32_t t, uint64_t seed, int64_t first,
         return fail(h, ROM_E_NOMEM, "host allocation failed");
     }
 }
+
+}  // extern "C"
+
+// ------------------------------------------------------------------------------------ slab
+namespace {
+
+int slab_fail(rom_slab* sl, int code, const std::string& msg)
+{
+    if (sl) sl->err = msg;
+    else g_create_error = msg;
+    return code;
+}
+
+template <typename T>
+std::vector<T> to_type(const double* p, size_t n)
+{
+    return std::vector<T>(p, p + n);
+}
+
+template <typename T>
+int slab_run(rom_slab* sl, int t, int n, const double* mu, const double* w, const double* inflow, const rom_si_opts& o,
+             double* phis, int32_t* iters, rom_ens_stats* stats)
+{
+    const int nn = sl->nx + 1;
+    const bool fp64 = sizeof(T) == 8;
+    // lanes per system: enough for the ordinates (at most 64 per lane), more when the wavefront's
+    // LDS (three [nn] arrays per system) would exceed 48 KiB
+    int L = 1;
+    while (L < 64 && L < n) L *= 2;
+    while (L < 64 && slab_lds_bytes(fp64, nn, L) > 48 * 1024) L *= 2;
+    if (slab_lds_bytes(fp64, nn, L) > 64 * 1024) return slab_fail(sl, ROM_E_UNSUPPORTED, "slab grid too large for LDS");
+    const int K = (n + L - 1) / L;
+    const int kmax = K <= 1 ? 1 : K <= 4 ? 4 : K <= 16 ? 16 : 64;
+    hipStream_t s = sl->stream();
+    DevMem d_mu, d_w, d_in, d_st, d_ss, d_q, d_phi, d_it, d_state, d_r;
+    upload(d_mu, to_type<T>(mu, (size_t)t * n));
+    upload(d_w, to_type<T>(w, (size_t)t * n));
+    upload(d_in, to_type<T>(inflow, (size_t)t * n));
+    upload(d_st, to_type<T>(sl->st.data(), nn));
+    upload(d_ss, to_type<T>(sl->ss.data(), nn));
+    upload(d_q, to_type<T>(sl->q.data(), nn));
+    HIPCHK(d_phi.alloc((size_t)t * nn * sizeof(T)));
+    HIPCHK(d_it.alloc((size_t)t * 4));
+    HIPCHK(d_state.alloc((size_t)t * 4));
+    HIPCHK(d_r.alloc((size_t)t * 8));
+    SlabArgs a{};
+    a.mu = d_mu.p;
+    a.w = d_w.p;
+    a.inflow = d_in.p;
+    a.st = d_st.p;
+    a.ss = d_ss.p;
+    a.q = d_q.p;
+    a.phi = d_phi.p;
+    a.iters = d_it.as<int32_t>();
+    a.state = d_state.as<int32_t>();
+    a.rfinal = d_r.as<double>();
+    a.nsys = t;
+    a.n = n;
+    a.nn = nn;
+    a.L = L;
+    a.max_iter = o.max_iter;
+    a.tol = o.tol;
+    a.inv_dx = (double)sl->nx / (sl->x1 - sl->x0);
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    HIPCHK(hipEventRecord(e0, s));
+    HIPCHK(launch_slab(a, fp64, kmax, s));
+    HIPCHK(hipEventRecord(e1, s));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    std::vector<T> ph((size_t)t * nn);
+    std::vector<int32_t> it(t), st(t);
+    HIPCHK(hipMemcpy(ph.data(), d_phi.p, ph.size() * sizeof(T), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(it.data(), d_it.p, (size_t)t * 4, hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(st.data(), d_state.p, (size_t)t * 4, hipMemcpyDeviceToHost));
+    for (size_t k = 0; k < ph.size(); ++k) phis[k] = (double)ph[k];
+    int worst = ROM_OK, mn = 1 << 30, mx = 0;
+    int64_t upd = 0;
+    for (int k = 0; k < t; ++k) {
+        if (iters) iters[k] = it[k];
+        mn = std::min(mn, it[k]);
+        mx = std::max(mx, it[k]);
+        upd += (int64_t)it[k] * n * sl->nx;
+        if (st[k] == 3) worst = ROM_E_DIVERGED;
+        else if (st[k] != 1 && worst == ROM_OK) worst = ROM_NOT_CONVERGED;
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->samples = t;
+        stats->min_iters = mn;
+        stats->max_iters = mx;
+        stats->status = worst == ROM_OK ? ROM_OK : ROM_NOT_CONVERGED;
+        stats->updates = upd;
+        stats->device_ms = ms;
+        stats->lanes = L;
+    }
+    if (worst == ROM_E_DIVERGED) return slab_fail(sl, ROM_E_DIVERGED, "non-finite iterate in a slab system");
+    return worst;
+}
+
+}  // namespace
+
+extern "C" {
+
+int rom_slab_create(int32_t nx, double x0, double x1, const double* sigma_t, const double* sigma_s, const double* q,
+                    rom_slab** out)
+{
+    if (!out) return slab_fail(nullptr, ROM_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (!sigma_t || !sigma_s || !q) return slab_fail(nullptr, ROM_E_ARG, "NULL field");
+    if (nx < 1 || nx > (1 << 24)) return slab_fail(nullptr, ROM_E_ARG, "nx must be in 1 .. 2^24");
+    if (!isfin(x0) || !isfin(x1) || !(x1 > x0)) return slab_fail(nullptr, ROM_E_ARG, "need x1 > x0");
+    for (int i = 0; i <= nx; ++i) {
+        const double st = sigma_t[i], ss = sigma_s[i], qq = q[i];
+        if (!isfin(st) || !isfin(ss) || !isfin(qq)) return slab_fail(nullptr, ROM_E_DOMAIN, "non-finite field value");
+        if (!(st > 0.0)) return slab_fail(nullptr, ROM_E_DOMAIN, "sigma_t must be > 0");
+        if (ss < 0.0 || !(ss < st)) return slab_fail(nullptr, ROM_E_DOMAIN, "need 0 <= sigma_s < sigma_t");
+        if (qq < 0.0) return slab_fail(nullptr, ROM_E_DOMAIN, "q must be >= 0");
+    }
+    try {
+        rom_slab* sl = new rom_slab();
+        sl->nx = nx;
+        sl->x0 = x0;
+        sl->x1 = x1;
+        sl->st.assign(sigma_t, sigma_t + nx + 1);
+        sl->ss.assign(sigma_s, sigma_s + nx + 1);
+        sl->q.assign(q, q + nx + 1);
+        *out = sl;
+        return ROM_OK;
+    } catch (const std::bad_alloc&) {
+        return slab_fail(nullptr, ROM_E_NOMEM, "host allocation failed");
+    }
+}
+
+void rom_slab_destroy(rom_slab* sl) { delete sl; }
+
+int rom_slab_set_stream(rom_slab* sl, void* stream)
+{
+    if (!sl) return ROM_E_ARG;
+    sl->user_stream = (hipStream_t)stream;
+    return ROM_OK;
+}
+
+int rom_slab_solve(rom_slab* sl, int32_t t, int32_t n, const double* mu, const double* w, const double* inflow,
+                   const rom_si_opts* opts, double* phis, int32_t* iters, rom_ens_stats* stats)
+{
+    if (!sl) return ROM_E_ARG;
+    if (t < 1 || n < 1 || n > 4096) return slab_fail(sl, ROM_E_ARG, "need t >= 1 and 1 <= n <= 4096");
+    if (!mu || !w || !inflow || !phis) return slab_fail(sl, ROM_E_ARG, "NULL mu, w, inflow or phis");
+    rom_si_opts o;
+    std::memset(&o, 0, sizeof(o));
+    if (opts) o = *opts;
+    if (!isfin(o.tol)) return slab_fail(sl, ROM_E_ARG, "tol must be finite");
+    if (o.tol == 0.0) o.tol = 1e-6;
+    if (o.max_iter < 0) return slab_fail(sl, ROM_E_ARG, "max_iter must be >= 0");
+    if (o.max_iter == 0) o.max_iter = 1000;
+    if (o.precision != ROM_PREC_FP32 && o.precision != ROM_PREC_FP64) return slab_fail(sl, ROM_E_ARG, "bad precision");
+    for (int k = 0; k < t; ++k) {
+        double sum = 0.0;
+        for (int l = 0; l < n; ++l) {
+            const size_t i = (size_t)k * n + l;
+            if (!isfin(mu[i]) || mu[i] == 0.0 || std::fabs(mu[i]) > 1.0)
+                return slab_fail(sl, ROM_E_DOMAIN, "every mu must satisfy 0 < |mu| <= 1");
+            if (!isfin(w[i]) || !(w[i] > 0.0)) return slab_fail(sl, ROM_E_DOMAIN, "weights must be > 0");
+            if (!isfin(inflow[i]) || inflow[i] < 0.0) return slab_fail(sl, ROM_E_DOMAIN, "inflow must be finite and >= 0");
+            sum += w[i];
+        }
+        if (std::fabs(sum - 1.0) > 1e-12) return slab_fail(sl, ROM_E_DOMAIN, "weights of a system must sum to 1");
+    }
+    try {
+        return o.precision == ROM_PREC_FP64 ? slab_run<double>(sl, t, n, mu, w, inflow, o, phis, iters, stats)
+                                            : slab_run<float>(sl, t, n, mu, w, inflow, o, phis, iters, stats);
+    } catch (const Fail& f) {
+        return slab_fail(sl, f.code, f.msg);
+    } catch (const std::bad_alloc&) {
+        return slab_fail(sl, ROM_E_NOMEM, "host allocation failed");
+    }
+}
+
+int rom_slab_ordinates(int32_t kind, int32_t n, uint64_t seed, int64_t sample, double* mu, double* w)
+{
+    if (!mu || !w || n < 1 || sample < 0) return ROM_E_ARG;
+    return slab_ordinates(kind, n, seed, sample, mu, w);
+}
+
+const char* rom_slab_last_error(const rom_slab* sl) { return sl ? sl->err.c_str() : g_create_error.c_str(); }
 
 }  // extern "C"

@@ -104,6 +104,28 @@ struct ContractArgs {
     const SysCtl* sysctl;      // skip when that system has stopped (NULL: always run)
 };
 
+// Slab systems (Sec. 4.1): all share one problem (fields at the nn grid points), each has its own
+// n ordinates; a wavefront holds 64 / L systems of L lanes, a lane carries ordinates r, r + L, ...
+struct SlabArgs {
+    const void* mu;            // [nsys][n] (T)
+    const void* w;             // [nsys][n] (T)
+    const void* inflow;        // [nsys][n] (T), entry-face value of each ordinate
+    const void* st;            // [nn] sigma_t at the grid points (T)
+    const void* ss;            // [nn]
+    const void* q;             // [nn]
+    void* phi;                 // [nsys][nn] (T), last iterate
+    int32_t* iters;            // [nsys]
+    int32_t* state;            // [nsys]: 1 converged, 2 stopped at max_iter, 3 diverged
+    double* rfinal;            // [nsys] last relative change
+    int32_t nsys, n, nn, L;    // systems, ordinates per system, grid points, lanes per system
+    int32_t max_iter, pad;
+    double tol;
+    double inv_dx;
+};
+// kmax: ordinates per lane the variant holds (1, 4, 16 or 64; >= ceil(n / L))
+size_t slab_lds_bytes(bool fp64, int nn, int L);
+hipError_t launch_slab(const SlabArgs& a, bool fp64, int kmax, hipStream_t s);
+
 // L = lanes per ordinate group (16, 32 or 64; 64 for anisotropic sources and psi output);
 // mom = 1 (isotropic source) or 4 (linear kernel: three source planes, four moment planes)
 hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty, bool dd, bool ang, int psi, int L,

@@ -196,6 +196,51 @@ int generate_ordinates(const rom_ord_spec& sp, uint64_t seed, int64_t sample, do
     }
 }
 
+// Slab ordinates (Sec. 4.1), weights normalized to sum 1 (the paper's 2/n with the 1/2 of the
+// slab average folded in).  RANDOM: [-1, 1] in n equal cells (n even), one uniform draw in each
+// cell of [-1, 0] (in order from -1, sample's own stream), the cells of [0, 1] receive the mirror
+// images mu_l = -mu_{n+1-l}.  GAUSS: Gauss-Legendre nodes in decreasing order.  UNIFORM: the
+// midpoints of n equal cells.
+int slab_ordinates(int kind, int n, uint64_t seed, int64_t sample, double* mu, double* w)
+{
+    if (n <= 0 || !mu || !w) return ROM_E_ARG;
+    switch (kind) {
+    case ROM_SLAB_RANDOM: {
+        if (n & 1) return ROM_E_ARG;
+        SplitMix64 rng(stream_seed(seed, sample));
+        const double width = 2.0 / double(n);
+        for (int l = 0; l < n / 2; ++l) {
+            const double u = rng.uniform();
+            mu[l] = -1.0 + double(l) * width + u * width;
+        }
+        for (int l = n / 2; l < n; ++l) mu[l] = -mu[n - 1 - l];
+        for (int l = 0; l < n; ++l) w[l] = 1.0 / double(n);
+        return ROM_OK;
+    }
+    case ROM_SLAB_GAUSS: {
+        // roots of P_n: the positive ones (decreasing), then their negatives, then 0 for odd n
+        const std::vector<double> pos = positive_legendre_roots(n, n / 2);
+        int l = 0;
+        for (int i = 0; i < n / 2; ++i) mu[l++] = pos[i];
+        if (n & 1) mu[l++] = 0.0;
+        for (int i = n / 2 - 1; i >= 0; --i) mu[l++] = -pos[i];
+        for (int k = 0; k < n; ++k) {
+            double p, dp;
+            legendre_pd(n, mu[k], p, dp);
+            w[k] = 1.0 / (((1.0 - mu[k]) * (1.0 + mu[k])) * dp * dp);  // Gauss weight 2/(...) halved
+        }
+        return ROM_OK;
+    }
+    case ROM_SLAB_UNIFORM:
+        for (int l = 0; l < n; ++l) {
+            mu[l] = -1.0 + (2.0 * l + 1.0) / double(n);
+            w[l] = 1.0 / double(n);
+        }
+        return ROM_OK;
+    default: return ROM_E_ARG;
+    }
+}
+
 // Scattering phase function of the cosine between two 3-D directions, folded over +-zeta':
 // X-Y solutions are even in zeta, so each stored ordinate stands for the pair (c, s, +-zeta).
 double phase_folded(int kind, double g, const double* u, const double* v)

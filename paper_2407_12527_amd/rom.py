@@ -23,7 +23,9 @@ __all__ = [
     "solve_batch", "si_opts", "rom_create", "rom_destroy", "rom_set_stream", "rom_set_ordinates",
     "rom_set_inflow_angular", "rom_set_scattering", "rom_sweep", "rom_source_iterate", "rom_ensemble",
     "rom_ensemble_samples", "rom_solve_batch", "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
-    "rom_last_error", "rom_version",
+    "rom_last_error", "rom_version", "rom_slab_create", "rom_slab_destroy", "rom_slab_set_stream", "rom_slab_solve",
+    "rom_slab_ordinates", "rom_slab_last_error", "ROM_SLAB_RANDOM", "ROM_SLAB_GAUSS", "ROM_SLAB_UNIFORM", "Slab",
+    "slab_ordinates",
 ]
 
 ROM_OK, ROM_NOT_CONVERGED = 0, 1
@@ -36,13 +38,15 @@ ROM_ORD_STRATIFIED, ROM_ORD_IID_SPHERE, ROM_ORD_UNIFORM2D, ROM_ORD_GAUSS2D = 0, 
 ROM_PREC_FP32, ROM_PREC_FP64 = 0, 1
 ROM_SWEEP_AUTO, ROM_SWEEP_STRIP, ROM_SWEEP_DIAG = 0, 1, 2
 ROM_FACE_LEFT, ROM_FACE_RIGHT, ROM_FACE_BOTTOM, ROM_FACE_TOP = 0, 1, 2, 3
+ROM_SLAB_RANDOM, ROM_SLAB_GAUSS, ROM_SLAB_UNIFORM = 0, 1, 2
 
 # every function declared in include/rom.h
 EXPORTS = ("rom_create", "rom_destroy", "rom_set_stream", "rom_set_ordinates", "rom_set_inflow_angular",
            "rom_set_scattering", "rom_sweep", "rom_source_iterate", "rom_ensemble", "rom_ensemble_samples",
            "rom_solve_batch",
            "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
-           "rom_last_error", "rom_version")
+           "rom_last_error", "rom_version", "rom_slab_create", "rom_slab_destroy", "rom_slab_set_stream",
+           "rom_slab_solve", "rom_slab_ordinates", "rom_slab_last_error")
 
 
 class rom_grid(C.Structure):
@@ -124,6 +128,15 @@ def lib():
         L.rom_last_error.argtypes = [P]
         L.rom_last_error.restype = C.c_char_p
         L.rom_version.restype = C.c_char_p
+        L.rom_slab_create.argtypes = [C.c_int32, C.c_double, C.c_double, P, P, P, PH]
+        L.rom_slab_destroy.argtypes = [P]
+        L.rom_slab_destroy.restype = None
+        L.rom_slab_set_stream.argtypes = [P, P]
+        L.rom_slab_solve.argtypes = [P, C.c_int32, C.c_int32, P, P, P, C.POINTER(rom_si_opts), P, P,
+                                     C.POINTER(rom_ens_stats)]
+        L.rom_slab_ordinates.argtypes = [C.c_int32, C.c_int32, C.c_uint64, C.c_int64, P, P]
+        L.rom_slab_last_error.argtypes = [P]
+        L.rom_slab_last_error.restype = C.c_char_p
         _lib = L
     return _lib
 
@@ -167,6 +180,30 @@ def rom_ensemble(h, t, seed, spec, opts, mean, var, stats):
 
 def rom_ensemble_samples(h, t, seed, first, spec, opts, phis, stats):
     return lib().rom_ensemble_samples(h, t, seed, first, spec, opts, phis, stats)
+
+
+def rom_slab_create(nx, x0, x1, sigma_t, sigma_s, q, out):
+    return lib().rom_slab_create(nx, x0, x1, sigma_t, sigma_s, q, out)
+
+
+def rom_slab_destroy(s):
+    return lib().rom_slab_destroy(s)
+
+
+def rom_slab_set_stream(s, stream):
+    return lib().rom_slab_set_stream(s, stream)
+
+
+def rom_slab_solve(s, t, n, mu, w, inflow, opts, phis, iters, stats):
+    return lib().rom_slab_solve(s, t, n, mu, w, inflow, opts, phis, iters, stats)
+
+
+def rom_slab_ordinates(kind, n, seed, sample, mu, w):
+    return lib().rom_slab_ordinates(kind, n, seed, sample, mu, w)
+
+
+def rom_slab_last_error(s):
+    return lib().rom_slab_last_error(s)
 
 
 def rom_solve_batch(hs, k, opts, phis, stats):
@@ -381,3 +418,54 @@ def _hip_memcpy_d2d(dst, src, nbytes):
     rc = _hip.hipMemcpy(C.c_void_p(dst), C.c_void_p(src), nbytes, 3)  # hipMemcpyDeviceToDevice
     if rc != 0:
         raise RomError(ROM_E_DEVICE, f"hipMemcpy failed ({rc})")
+
+
+# ------------------------------------------------------------------ slab geometry (Sec. 4.1)
+def slab_ordinates(kind, n, seed=0, sample=0):
+    """Slab ordinate set (host only): ROM_SLAB_RANDOM (sample of seed), ROM_SLAB_GAUSS or
+    ROM_SLAB_UNIFORM; weights sum to 1."""
+    mu = np.empty(n)
+    w = np.empty(n)
+    _check(lib().rom_slab_ordinates(kind, n, seed, sample, _ptr(mu), _ptr(w)))
+    return mu, w
+
+
+class Slab:
+    """Owns one ``rom_slab*``: a slab problem with fields at the nx + 1 grid points."""
+
+    def __init__(self, nx, sigma_t, sigma_s, q, x0=0.0, x1=1.0):
+        self.nx = int(nx)
+        self.s = None
+        out = C.c_void_p()
+        st, ss, qq = _f64(sigma_t, nx + 1), _f64(sigma_s, nx + 1), _f64(q, nx + 1)
+        rc = lib().rom_slab_create(self.nx, x0, x1, _ptr(st), _ptr(ss), _ptr(qq), C.byref(out))
+        if rc != ROM_OK:
+            raise RomError(rc, (lib().rom_slab_last_error(None) or b"").decode())
+        self.s = out.value
+
+    def close(self):
+        if self.s:
+            lib().rom_slab_destroy(self.s)
+            self.s = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def solve(self, mu, w, inflow, opts=None):
+        """t systems: mu, w, inflow are [t, n] (or [n] for one system).  Returns phis [t, nx+1],
+        iterations [t], stats, status."""
+        mu = np.atleast_2d(_f64(mu))
+        t, n = mu.shape
+        w = _f64(w, t * n)
+        inflow = _f64(inflow, t * n)
+        phis = np.empty((t, self.nx + 1))
+        iters = np.zeros(t, dtype=np.int32)
+        st = rom_ens_stats()
+        rc = lib().rom_slab_solve(self.s, t, n, _ptr(mu), _ptr(w), _ptr(inflow), C.byref(opts) if opts else None,
+                                  _ptr(phis), iters.ctypes.data, C.byref(st))
+        if rc < 0:
+            raise RomError(rc, (lib().rom_slab_last_error(self.s) or b"").decode())
+        return phis, iters, st, rc

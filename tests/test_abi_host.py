@@ -173,3 +173,54 @@ def test_batch_argument_checks(R):
         assert R.rom_solve_batch(hs, 2, None, None, None) == R.ROM_E_STATE  # no ordinates yet
     finally:
         R.rom_destroy(h)
+
+
+# ------------------------------------------------------------------ slab geometry (host side)
+@pytest.mark.parametrize("n", [2, 4, 8, 16, 64])
+def test_slab_rom_ordinates_bit_identical_to_oracle(R, orc, n):
+    for seed, sample in ((0, 0), (2024, 5), (7, 123456)):
+        mu, w = R.slab_ordinates(R.ROM_SLAB_RANDOM, n, seed, sample)
+        mo, wo = orc.slab_rom_ordinates(n, seed, sample)
+        assert np.array_equal(mu, mo) and np.array_equal(w, wo)
+
+
+def test_slab_quadratures_match_oracle(R, orc):
+    for n in (2, 7, 16, 2560):
+        mu, w = R.slab_ordinates(R.ROM_SLAB_GAUSS, n)
+        mo, wo = orc.slab_quadrature(orc.SLAB_GAUSS, n)
+        np.testing.assert_allclose(mu, mo, atol=2e-15)
+        np.testing.assert_allclose(w, wo, rtol=1e-11)
+        assert abs(w.sum() - 1) < 1e-13
+    mu, w = R.slab_ordinates(R.ROM_SLAB_UNIFORM, 10)
+    mo, wo = orc.slab_quadrature(orc.SLAB_UNIFORM, 10)
+    assert np.array_equal(mu, mo) and np.array_equal(w, wo)
+    with pytest.raises(R.RomError):
+        R.slab_ordinates(R.ROM_SLAB_RANDOM, 5)   # odd n has no mirror pairs
+    with pytest.raises(R.RomError):
+        R.slab_ordinates(9, 4)
+
+
+def test_slab_create_and_solve_validation(R):
+    nx = 8
+    x = np.linspace(0, 1, nx + 1)
+    st, ss, q = 1 + x, 0.5 * (1 + x), np.ones(nx + 1)
+    with pytest.raises(R.RomError):
+        R.Slab(nx, st, st, q)                      # sigma_s must be < sigma_t
+    with pytest.raises(R.RomError):
+        R.Slab(nx, st, ss, -q)                     # q >= 0
+    with pytest.raises(R.RomError):
+        R.Slab(0, st[:1], ss[:1], q[:1])           # nx >= 1
+    s = R.Slab(nx, st, ss, q)
+    mu, w = R.slab_ordinates(R.ROM_SLAB_RANDOM, 4, 1, 0)
+    bad = [(np.where(mu > 0, 0.0, mu), w, np.ones(4)),      # mu = 0
+           (mu, w * 1.01, np.ones(4)),                     # weights off 1
+           (mu, w, -np.ones(4)),                           # negative inflow
+           (np.where(mu > 0, 1.5, mu), w, np.ones(4))]     # |mu| > 1
+    for m, ww, inf in bad:
+        with pytest.raises(R.RomError) as e:
+            s.solve(m, ww, inf)
+        assert e.value.status == R.ROM_E_DOMAIN
+    o = R.si_opts()
+    o.precision = 7
+    with pytest.raises(R.RomError):
+        s.solve(mu, w, np.ones(4), o)

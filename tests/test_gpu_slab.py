@@ -1,0 +1,96 @@
+"""GPU parity of the slab-geometry solver (Sec. 4.1, Example 4.1) against the FP64 oracle on
+bit-identical ordinate sets: the three inflow cases, ROM sets of n = 2..16, many systems per
+launch with a ragged last wavefront, large quadratures (several ordinates per lane, up to the
+2560-ordinate reference), long grids (more lanes per system for LDS), FP64 at fixed iteration
+counts (1e-12 relative, max-norm) and FP32 to convergence (1e-5 normwise)."""
+import numpy as np
+import pytest
+
+import rom_inputs as RI
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def R():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2407_12527_amd import rom
+    rom.lib()
+    return rom
+
+
+def nrm(a, b):
+    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
+
+
+def oracle_phi(orc, f, mu, w, tol, max_iter):
+    return orc.slab_source_iterate(f.nx, f.x0, f.x1, f.sigma_t, f.sigma_s, f.q, mu, w, f.inflow(mu), tol=tol,
+                                   max_iter=max_iter)
+
+
+@pytest.mark.parametrize("case", [1, 2, 3])
+@pytest.mark.parametrize("n", [2, 4, 8, 16])
+def test_rom_sets_fixed_iterations_fp64(R, orc, case, n):
+    f = RI.slab_example41(50, case)
+    s = R.Slab(f.nx, f.sigma_t, f.sigma_s, f.q)
+    t = 37   # not a multiple of the systems per wavefront
+    mus, ws = zip(*(R.slab_ordinates(R.ROM_SLAB_RANDOM, n, 2024, k) for k in range(t)))
+    mu, w = np.array(mus), np.array(ws)
+    phis, iters, st, rc = s.solve(mu, w, f.inflow(mu), R.si_opts(tol=-1.0, max_iter=7, precision=R.ROM_PREC_FP64))
+    assert rc == R.ROM_NOT_CONVERGED and np.all(iters == 7)
+    for k in range(t):
+        ref = oracle_phi(orc, f, mu[k], w[k], 0.0, 7)["phi"]
+        assert np.max(np.abs(phis[k] - ref)) <= 1e-12 * np.max(np.abs(ref)), k
+
+
+@pytest.mark.parametrize("case", [1, 3])
+def test_converged_fp32_and_fp64(R, orc, case):
+    f = RI.slab_example41(50, case)
+    s = R.Slab(f.nx, f.sigma_t, f.sigma_s, f.q)
+    mus, ws = zip(*(R.slab_ordinates(R.ROM_SLAB_RANDOM, 8, 3, k) for k in range(100)))
+    mu, w = np.array(mus), np.array(ws)
+    p32, it32, _, rc = s.solve(mu, w, f.inflow(mu), R.si_opts(tol=1e-6))
+    assert rc == 0
+    p64, it64, _, rc = s.solve(mu, w, f.inflow(mu), R.si_opts(tol=1e-12, precision=R.ROM_PREC_FP64))
+    assert rc == 0
+    for k in (0, 41, 99):
+        ref = oracle_phi(orc, f, mu[k], w[k], 1e-13, 10000)
+        assert nrm(p32[k], ref["phi"]) < 1e-5
+        assert nrm(p64[k], ref["phi"]) < 1e-11
+        # same stopping rule, same tolerance: the same iteration (up to a rounding tie)
+        assert abs(int(it64[k]) - oracle_phi(orc, f, mu[k], w[k], 1e-12, 10000)["iters"]) <= 1
+
+
+@pytest.mark.parametrize("kind,n", [("gauss", 2560), ("gauss", 100), ("uniform", 64), ("gauss", 6)])
+def test_quadratures_many_ordinates_per_lane(R, orc, kind, n):
+    f = RI.slab_example41(50, 2)
+    s = R.Slab(f.nx, f.sigma_t, f.sigma_s, f.q)
+    mu, w = R.slab_ordinates(R.ROM_SLAB_GAUSS if kind == "gauss" else R.ROM_SLAB_UNIFORM, n)
+    phi, iters, st, rc = s.solve(mu, w, f.inflow(mu), R.si_opts(tol=-1.0, max_iter=6, precision=R.ROM_PREC_FP64))
+    ref = oracle_phi(orc, f, mu, w, 0.0, 6)["phi"]
+    assert np.max(np.abs(phi[0] - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("nx", [1, 3, 1000])
+def test_grid_sizes(R, orc, nx):
+    f = RI.slab_example41(nx, 1)
+    s = R.Slab(f.nx, f.sigma_t, f.sigma_s, f.q)
+    mus, ws = zip(*(R.slab_ordinates(R.ROM_SLAB_RANDOM, 6, 9, k) for k in range(5)))
+    mu, w = np.array(mus), np.array(ws)
+    phis, _, st, rc = s.solve(mu, w, f.inflow(mu), R.si_opts(tol=-1.0, max_iter=5, precision=R.ROM_PREC_FP64))
+    for k in range(5):
+        ref = oracle_phi(orc, f, mu[k], w[k], 0.0, 5)["phi"]
+        assert np.max(np.abs(phis[k] - ref)) <= 1e-12 * np.max(np.abs(ref)), k
+
+
+def test_odd_gauss_order_has_mu_zero_and_is_refused(R):
+    """An odd Gauss-Legendre order has the node mu = 0, where the slab equation has no sweep
+    direction; the solver refuses it (before any device work)."""
+    f = RI.slab_example41(10, 1)
+    s = R.Slab(f.nx, f.sigma_t, f.sigma_s, f.q)
+    mu, w = R.slab_ordinates(R.ROM_SLAB_GAUSS, 7)
+    with pytest.raises(R.RomError) as e:
+        s.solve(mu, w, f.inflow(mu))
+    assert e.value.status == R.ROM_E_DOMAIN
