@@ -94,3 +94,51 @@ def test_odd_gauss_order_has_mu_zero_and_is_refused(R):
     with pytest.raises(R.RomError) as e:
         s.solve(mu, w, f.inflow(mu))
     assert e.value.status == R.ROM_E_DOMAIN
+
+
+def _table2():
+    import os
+    out = {}
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "table2.txt")
+    for line in open(path):
+        if line.strip() and not line.startswith("#"):
+            q, case, n, v = line.split()
+            out[(q, int(case), int(n))] = float(v)
+    return out
+
+
+@pytest.mark.parametrize("case", [1, 2, 3])
+def test_table2_error_orders(R, case):
+    """Table 2 setting (t = 20 480, reference 2560 Gauss ordinates).  The expected per-sample
+    error E is compared with the printed values to 3 % at n = 2, 4, 5 % at n = 8 and 12 % at n = 16, where the
+    paper's second-order scheme (not given in its text) and this diamond difference part most, and
+    its order in Delta mu to 0.07; the bias (Monte Carlo noise at n = 16) must fall faster than
+    the error, and the Monte Carlo error must decay as t^-1/2 (slope within 0.05)."""
+    T = _table2()
+    f = RI.slab_example41(50, case)
+    s = R.Slab(f.nx, f.sigma_t, f.sigma_s, f.q)
+    mu, w = R.slab_ordinates(R.ROM_SLAB_GAUSS, 2560)
+    ref = s.solve(mu, w, f.inflow(mu), R.si_opts(tol=1e-13, max_iter=20000, precision=R.ROM_PREC_FP64))[0][0]
+    o = R.si_opts(tol=1e-12, max_iter=20000, precision=R.ROM_PREC_FP64)
+    t = 20480
+    E, B, dm = [], [], []
+    for n in (2, 4, 8, 16):
+        sets = [R.slab_ordinates(R.ROM_SLAB_RANDOM, n, 2024, k) for k in range(t)]
+        mus = np.array([m for m, _ in sets])
+        ws = np.array([x for _, x in sets])
+        phis, _, _, rc = s.solve(mus, ws, f.inflow(mus), o)
+        assert rc == 0
+        E.append(np.sqrt(np.mean((phis - ref) ** 2, axis=1)).mean())
+        mean = phis.mean(axis=0)
+        B.append(np.sqrt(np.mean((mean - ref) ** 2)))
+        dm.append(2.0 / n)
+        assert abs(E[-1] / T[("E", case, n)] - 1) < {2: 0.03, 4: 0.03, 8: 0.05, 16: 0.12}[n], (n, E[-1])
+        # Monte Carlo error of 16-sample averages against 1-sample spread: ratio 1/4
+        blk = phis.reshape(t // 16, 16, -1).mean(axis=1)
+        e16 = np.sqrt(np.mean((blk - mean) ** 2))
+        e1 = np.sqrt(np.mean((phis - mean) ** 2))
+        assert abs(np.log(e16 / e1) / np.log(16) + 0.5) < 0.05
+    order_E = np.polyfit(np.log(dm), np.log(E), 1)[0]
+    order_B = np.polyfit(np.log(dm), np.log(B), 1)[0]
+    assert abs(order_E - T[("order_E", case, 0)]) < 0.07
+    assert order_B > order_E + 0.5
