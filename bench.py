@@ -40,8 +40,8 @@ KERNEL_SOURCES = {
               "rom_sweep_f32_8x4.hip", "rom_sweep_f32_8x8.hip", "rom_sweep_f64.hip"],
 }
 MEASURED_TRAFFIC = {  # workload: (kernel family, shape as in config, source hash, bytes per launch)
-    "c2": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "8c9c77a7a2842fc1", 38476813),
-    "c1": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 1}, "8c9c77a7a2842fc1", 1809342),
+    "c2": ("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 1, "waves_per_group": 4}, "3370bd4af69bd06d", 25594011),
+    "c1": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 1}, "3370bd4af69bd06d", 1798402),
     "c3": ("strip", {"sweep_tile": "16x16", "band": 4}, "6c2c5693091b649e", 935117138),
 }
 

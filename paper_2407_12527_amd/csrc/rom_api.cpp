@@ -208,6 +208,7 @@ struct Plan {
     std::vector<uint16_t> h_bt16;
     int cells_per_block = 1024;
     int many_cpt = 0;  // many-slot combine: cells per thread (0: the few-slot combine)
+    int vec = 0;       // many-slot combine with 16-byte loads
     // row-lane sweep
     int kind = ROM_SWEEP_STRIP;
     int dR = 16, dK = 1, dNB = 1;
@@ -304,6 +305,7 @@ struct Plan {
         c.blocks = d_cblocks.as<int2>();
         c.cells_per_block = cells_per_block;
         c.many_cpt = many_cpt;
+        c.vec = vec;
         c.nsys = nsys;
         c.nmom = nmom;
         c.mom_r = mom_r;
@@ -349,6 +351,13 @@ rom_handle::~rom_handle()
 }
 
 namespace {
+
+// The vector-load many-slot combine is the default; ROM_VEC_COMBINE=0 selects the scalar one.
+bool vec_combine_enabled()
+{
+    const char* e = std::getenv("ROM_VEC_COMBINE");
+    return !(e && e[0] == '0');
+}
 
 int device_cus()
 {
@@ -882,7 +891,15 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         for (auto& si : in) tot += si.h->cells;
         for (auto& sd : P.sys) maxslots = std::max(maxslots, sd.nslots);
         P.many_cpt = 0;
-        if (maxslots > 8 && P.nmom == 1) {
+        P.vec = 0;
+        // 16-byte loads when every partial plane starts and ends on a 16-byte boundary
+        const int V = P.fp64 ? 2 : 4;
+        bool aligned = true;
+        for (auto& si : in) aligned = aligned && si.h->cells % V == 0;
+        if (maxslots > 8 && P.nmom == 1 && aligned && vec_combine_enabled()) {
+            P.vec = 1;
+            P.cells_per_block = 64 * V;
+        } else if (maxslots > 8 && P.nmom == 1) {
             P.many_cpt = 1;
             while (P.many_cpt < 8 && tot / (64 * 2 * P.many_cpt) > 4 * device_cus()) P.many_cpt *= 2;
             P.cells_per_block = 64 * P.many_cpt;

@@ -75,9 +75,9 @@ struct SystemDev {
 constexpr int kDiagMaxWaves = 16;
 constexpr int kPoolPad = 128;   // elements of padding before and after the sigma_t and source pools
 
-// Row pitch (elements) of the row-lane sweep's y-face tables and band edges: a multiple of 8
-// with at least 8 elements of padding, so U-column runs past the row end stay inside.
-__host__ __device__ inline int diag_pitch(int nx) { return ((nx + 7) & ~7) + 8; }
+// Row pitch (elements) of the row-lane sweep's y-face tables and band edges: a multiple of 16
+// with at least 16 elements of padding, so U-column runs (U <= 16) past the row end stay inside.
+__host__ __device__ inline int diag_pitch(int nx) { return ((nx + 15) & ~15) + 16; }
 
 struct DiagTaskDev {
     int32_t sys, prob, quad;

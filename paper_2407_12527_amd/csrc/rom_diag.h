@@ -37,8 +37,12 @@ namespace rom {
 
 template <int R>
 constexpr int diag_ring() { return R == 16 ? 64 : 128; }
-template <typename T>
-constexpr int diag_unroll() { return sizeof(T) == 8 ? 4 : 8; }
+// Steps per block: each block boundary costs the hand-off waits, exports and publication, so
+// FP32 blocks are 16 steps long where the lane state still fits the VGPR budget (at most two
+// ordinates per lane and two prefetch sets, i.e. at most 8 waves per workgroup, 256 VGPRs);
+// otherwise 8.  FP64: 4.  (diag_pitch pads the y-face tables for 16.)
+template <typename T, int K, int PD>
+constexpr int diag_unroll() { return sizeof(T) == 8 ? 4 : (K <= 2 && PD == 2 ? 16 : 8); }
 // Most wavefronts per workgroup: 16, or 8 where the lane state needs more than 128 VGPRs (more
 // than one ordinate per lane, or loads kept PD = 2 blocks ahead).
 template <typename T, int K, int PD>
@@ -249,7 +253,7 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
 {
     constexpr int NG = kWave / R;
     constexpr int NO = NG * K;
-    constexpr int U = diag_unroll<T>();
+    constexpr int U = diag_unroll<T, K, PD>();
     constexpr int RING = diag_ring<R>();
     constexpr int DIR = XPOS ? 1 : -1;  // storage step per sweep column
     static_assert(RING % U == 0 && R % U == 0, "runs must stay aligned");

@@ -216,6 +216,82 @@ __global__ __launch_bounds__(256) void combine_many_kernel(CombineArgs A)
     combine_tail(A, run, s, dmax, pmax);
 }
 
+// Many-slot combine with vector loads: a block owns 64 lanes x 16 bytes of consecutive cells
+// (256 FP32 / 128 FP64 cells); its four waves take every fourth slot, each lane keeping U
+// 16-byte loads in flight in U independent accumulators, folded in a fixed order, then the waves'
+// totals are added as ((w0 + w1) + (w2 + w3)) -- deterministic for a given slot count.
+template <typename T>
+struct Vec16;
+template <>
+struct Vec16<float> {
+    using type = float4;
+};
+template <>
+struct Vec16<double> {
+    using type = double2;
+};
+
+template <typename T>
+__global__ __launch_bounds__(256) void combine_vec_kernel(CombineArgs A)
+{
+    using V4 = typename Vec16<T>::type;
+    constexpr int V = 16 / sizeof(T);
+    constexpr int U = 8;
+    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+    if (A.mode == 0 && A.ctl->active == 0) return;
+    const int2 blk = A.blocks[blockIdx.x];
+    const int s = blk.x;
+    const SystemDev& SD = A.sys[s];
+    const ProblemDev& P = A.probs[SD.prob];
+    const int cells = P.nx * P.ny;
+    const bool run = A.mode == 1 || A.sysctl[s].state == 0;
+    __shared__ T wsum[4][64 * V];
+    double dmax = 0.0, pmax = 0.0;
+    if (run) {
+        const T* __restrict__ part = (const T*)A.part;
+        const int ns = SD.nslots;
+        const int64_t* __restrict__ soff = A.slot_off;
+        const int32_t* __restrict__ sord = A.slot_order + SD.slot_first;
+        const int c0 = blk.y + lane * V;
+        const bool in = c0 < cells;  // cells is a multiple of V: a lane's V cells are all in or all out
+        V4 acc[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) acc[u] = V4{};
+        int k = wave;
+        for (; k + 4 * (U - 1) < ns; k += 4 * U) {
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+                if (in) acc[u] += *(const V4*)(part + soff[sord[k + 4 * u]] + c0);
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (in && k + 4 * u < ns) acc[u] += *(const V4*)(part + soff[sord[k + 4 * u]] + c0);
+        const V4 tot = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
+        const T* tv = (const T*)&tot;
+#pragma unroll
+        for (int i = 0; i < V; ++i) wsum[wave][lane * V + i] = tv[i];
+    }
+    __syncthreads();
+    if (run) {
+        T* __restrict__ phi = (T*)A.phi + SD.phi_off;
+        T* __restrict__ src = (T*)A.src + SD.src_off;
+        const T* __restrict__ ss = (const T*)A.sigma_s + P.field_off;
+        const T* __restrict__ q = (const T*)A.q + P.field_off;
+        for (int e = tid; e < 64 * V; e += 256) {
+            const int cell = blk.y + e;
+            if (cell < cells) {
+                const T v = (wsum[0][e] + wsum[1][e]) + (wsum[2][e] + wsum[3][e]);
+                const T old = phi[cell];
+                dmax = fmax(dmax, fabs((double)v - (double)old));
+                pmax = fmax(pmax, fabs((double)v));
+                phi[cell] = v;
+                src[cell] = fma(ss[cell], v, q[cell]);
+            }
+        }
+    }
+    combine_tail(A, run, s, dmax, pmax);
+}
+
 // Combine of the linear-kernel sweep (four partial planes per slot: phi, Jx~, Jy~, phi~): per
 // cell the fixed-order sums over the system's slots, phi, its change, and the three source planes
 // of the next sweep, S0 = sigma_s phi~ + q, S1 = sigma_s g Jx~, S2 = sigma_s g Jy~ (the folded
@@ -590,6 +666,12 @@ hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStrea
         return hipGetLastError();
     }
     if (a.nmom != 1) return hipErrorInvalidValue;
+    if (a.vec) {
+        if (a.cells_per_block != 64 * (fp64 ? 2 : 4)) return hipErrorInvalidValue;
+        if (fp64) hipLaunchKernelGGL(combine_vec_kernel<double>, dim3(nblocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(combine_vec_kernel<float>, dim3(nblocks), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     if (a.many_cpt > 0) {
         // block tiles of 64 * many_cpt cells (cells_per_block must match)
         if (a.cells_per_block != 64 * a.many_cpt) return hipErrorInvalidValue;
