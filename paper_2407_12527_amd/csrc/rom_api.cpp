@@ -899,6 +899,9 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         if (maxslots > 8 && P.nmom == 1 && aligned && vec_combine_enabled()) {
             P.vec = 1;
             P.cells_per_block = 64 * V;
+        } else if (P.nmom == 1 && aligned && vec_combine_enabled()) {
+            P.vec = 2;  // few slots: one thread sums all slots of 16 bytes of cells, 4 tiles
+            P.cells_per_block = 4 * 256 * V;
         } else if (maxslots > 8 && P.nmom == 1) {
             P.many_cpt = 1;
             while (P.many_cpt < 8 && tot / (64 * 2 * P.many_cpt) > 4 * device_cus()) P.many_cpt *= 2;

@@ -202,6 +202,50 @@ __device__ __forceinline__ void store_run(T* p, const T (&v)[U])
     }
 }
 
+// A run of N cells of one lane's row starting at storage index c0 and moving by DIR per step, as
+// 16-byte vector accesses that need only element alignment (the runs of a wave's lanes are skewed
+// by one cell per row, so they are not 16-byte aligned; gfx950 global memory accepts unaligned
+// vector accesses): one instruction per 16 bytes instead of one per cell.  DIR = -1 covers
+// [c0 - N + 1, c0] and reverses the order.  Runs shorter than a vector fall back to single cells.
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void load_row_run(const T* base, int64_t c0, T (&v)[N])
+{
+    constexpr int W = 16 / sizeof(T);
+    if constexpr (N % W == 0) {
+        typedef T VU __attribute__((ext_vector_type(W), aligned(sizeof(T))));
+        const T* p = base + (DIR > 0 ? c0 : c0 - (N - 1));
+#pragma unroll
+        for (int q = 0; q < N / W; ++q) {
+            const VU x = *reinterpret_cast<const VU*>(p + q * W);
+#pragma unroll
+            for (int m = 0; m < W; ++m) v[DIR > 0 ? q * W + m : N - 1 - (q * W + m)] = x[m];
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < N; ++u) v[u] = base[c0 + DIR * u];
+    }
+}
+
+template <typename T, int N, int DIR>
+__device__ __forceinline__ void store_row_run(T* base, int64_t c0, const T (&v)[N])
+{
+    constexpr int W = 16 / sizeof(T);
+    if constexpr (N % W == 0) {
+        typedef T VU __attribute__((ext_vector_type(W), aligned(sizeof(T))));
+        T* p = base + (DIR > 0 ? c0 : c0 - (N - 1));
+#pragma unroll
+        for (int q = 0; q < N / W; ++q) {
+            VU x;
+#pragma unroll
+            for (int m = 0; m < W; ++m) x[m] = v[DIR > 0 ? q * W + m : N - 1 - (q * W + m)];
+            *reinterpret_cast<VU*>(p + q * W) = x;
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < N; ++u) base[c0 + DIR * u] = v[u];
+    }
+}
+
 // Device-coherent runs for the band edges (8-byte relaxed agent-scope accesses: the producer and
 // the consumer band may sit on different XCDs).
 template <typename T, int U>
@@ -287,11 +331,8 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
     T pst[PD][U], pS[PD][U];
     auto fetch = [&](T (&fst)[U], T (&fS)[U], int t0) {
         const int64_t c0 = lane0 + (int64_t)DIR * t0;
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            fst[u] = D.st[c0 + DIR * u];
-            fS[u] = D.S[c0 + DIR * u];
-        }
+        load_row_run<T, U, DIR>(D.st, c0, fst);
+        load_row_run<T, U, DIR>(D.S, c0, fS);
     };
     const int tsteps = nx + R - 1;                          // steps with a cell in the block
     const int tend = R + U * ((nx + U - 1) / U);            // ... and until the last column is exported
@@ -398,10 +439,7 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
             T tot[U / 4];
             slot_sums<T, U>(acc, tot);
             if (mode == 0) {
-                if (row_ok) {
-#pragma unroll
-                    for (int v = 0; v < U / 4; ++v) pblk[DIR * (v + g * (U / 4))] = tot[v];
-                }
+                if (row_ok) store_row_run<T, U / 4, DIR>(D.part, lane0 + (int64_t)DIR * (t0 + g * (U / 4)), tot);
             } else {
 #pragma unroll
                 for (int v = 0; v < U / 4; ++v) {
@@ -412,10 +450,7 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
             }
         } else {
             if (mode == 0) {
-                if (row_ok) {
-#pragma unroll
-                    for (int u = 0; u < U; ++u) pblk[DIR * u] = acc[u];
-                }
+                if (row_ok) store_row_run<T, U, DIR>(D.part, lane0 + (int64_t)DIR * t0, acc);
             } else {
 #pragma unroll
                 for (int u = 0; u < U; ++u) {

@@ -70,8 +70,9 @@ struct CombineArgs {
     int32_t mode;              // 0: source-iteration step, 1: plain sum (single sweep)
     int32_t max_iter;
     int32_t mom_r;             // linear kernel: phi~ comes from plane 3 (else phi~ = phi)
-    int32_t vec;               // 1: the many-slot combine with 16-byte loads, tiles of 64 * 16 B of
-                               // cells (every system's cell count a multiple of 16 B / sizeof(T))
+    int32_t vec;               // 16-byte loads (every system's cell count a multiple of 16 B /
+                               // sizeof(T)): 1 many slots, tiles of 64 * 16 B of cells split over
+                               // the block's waves by slot; 2 at most 8 slots, 4 tiles of 256 * 16 B
     double tol;
     const void* part;
     void* phi;

@@ -292,6 +292,76 @@ __global__ __launch_bounds__(256) void combine_vec_kernel(CombineArgs A)
     combine_tail(A, run, s, dmax, pmax);
 }
 
+// Few-slot combine with vector loads (at most 8 slots, e.g. ensembles with one lane group per
+// quadrant): each thread owns 16 bytes of consecutive cells in each of the block's TPB tiles of
+// 256 * 16 bytes; it issues every load of all its tiles (one 16-byte load per slot, plus phi,
+// sigma_s and q) before any arithmetic or store, so a thread keeps up to TPB * 11 loads in flight,
+// and the block's convergence atomics are amortized over TPB tiles.  Slots are added as
+// ((s0 + s1) + (s2 + s3)) + ((s4 + s5) + (s6 + s7)).
+constexpr int kFewTiles = 4;
+
+template <typename T>
+__global__ __launch_bounds__(256) void combine_vec_few_kernel(CombineArgs A)
+{
+    using V4 = typename Vec16<T>::type;
+    constexpr int V = 16 / sizeof(T);
+    constexpr int TPB = kFewTiles;
+    if (A.mode == 0 && A.ctl->active == 0) return;
+    const int2 blk = A.blocks[blockIdx.x];
+    const int s = blk.x;
+    const SystemDev& SD = A.sys[s];
+    const ProblemDev& P = A.probs[SD.prob];
+    const int cells = P.nx * P.ny;
+    const bool run = A.mode == 1 || A.sysctl[s].state == 0;
+    double dmax = 0.0, pmax = 0.0;
+    if (run) {
+        const T* __restrict__ part = (const T*)A.part;
+        const T* __restrict__ ssp = (const T*)A.sigma_s + P.field_off;
+        const T* __restrict__ qp = (const T*)A.q + P.field_off;
+        T* __restrict__ phi = (T*)A.phi + SD.phi_off;
+        T* __restrict__ src = (T*)A.src + SD.src_off;
+        const int ns = SD.nslots;
+        const int64_t* __restrict__ soff = A.slot_off;
+        const int32_t* __restrict__ sord = A.slot_order + SD.slot_first;
+        const T* sp[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) sp[k] = k < ns ? part + soff[sord[k]] : nullptr;
+        V4 acc[TPB][8], old[TPB], ssv[TPB], qv[TPB];
+#pragma unroll
+        for (int t = 0; t < TPB; ++t) {
+            const int c0 = blk.y + t * 256 * V + (int)threadIdx.x * V;
+            const bool in = c0 < cells;  // cells is a multiple of V
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc[t][k] = (in && k < ns) ? *(const V4*)(sp[k] + c0) : V4{};
+            old[t] = in ? *(const V4*)(phi + c0) : V4{};
+            ssv[t] = in ? *(const V4*)(ssp + c0) : V4{};
+            qv[t] = in ? *(const V4*)(qp + c0) : V4{};
+        }
+#pragma unroll
+        for (int t = 0; t < TPB; ++t) {
+            const int c0 = blk.y + t * 256 * V + (int)threadIdx.x * V;
+            if (c0 >= cells) continue;
+            const V4 tot = ((acc[t][0] + acc[t][1]) + (acc[t][2] + acc[t][3])) +
+                           ((acc[t][4] + acc[t][5]) + (acc[t][6] + acc[t][7]));
+            const T* tv = (const T*)&tot;
+            const T* ov = (const T*)&old[t];
+            const T* sv = (const T*)&ssv[t];
+            const T* qq = (const T*)&qv[t];
+            V4 sn;
+            T* snv = (T*)&sn;
+#pragma unroll
+            for (int i = 0; i < V; ++i) {
+                dmax = fmax(dmax, fabs((double)tv[i] - (double)ov[i]));
+                pmax = fmax(pmax, fabs((double)tv[i]));
+                snv[i] = fma(sv[i], tv[i], qq[i]);
+            }
+            *(V4*)(phi + c0) = tot;
+            *(V4*)(src + c0) = sn;
+        }
+    }
+    combine_tail(A, run, s, dmax, pmax);
+}
+
 // Combine of the linear-kernel sweep (four partial planes per slot: phi, Jx~, Jy~, phi~): per
 // cell the fixed-order sums over the system's slots, phi, its change, and the three source planes
 // of the next sweep, S0 = sigma_s phi~ + q, S1 = sigma_s g Jx~, S2 = sigma_s g Jy~ (the folded
@@ -666,6 +736,12 @@ hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStrea
         return hipGetLastError();
     }
     if (a.nmom != 1) return hipErrorInvalidValue;
+    if (a.vec == 2) {
+        if (a.cells_per_block != kFewTiles * 256 * (fp64 ? 2 : 4)) return hipErrorInvalidValue;
+        if (fp64) hipLaunchKernelGGL(combine_vec_few_kernel<double>, dim3(nblocks), dim3(256), 0, s, a);
+        else hipLaunchKernelGGL(combine_vec_few_kernel<float>, dim3(nblocks), dim3(256), 0, s, a);
+        return hipGetLastError();
+    }
     if (a.vec) {
         if (a.cells_per_block != 64 * (fp64 ? 2 : 4)) return hipErrorInvalidValue;
         if (fp64) hipLaunchKernelGGL(combine_vec_kernel<double>, dim3(nblocks), dim3(256), 0, s, a);
