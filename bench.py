@@ -29,6 +29,8 @@ FLOPS_PER_UPDATE = 8
 FP32_VECTOR_PEAK_TFLOPS = 157.3   # MI355X datasheet, FP32 vector
 FP64_VECTOR_PEAK_TFLOPS = 78.6
 BF16_MFMA_PEAK_TFLOPS = 2500.0
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_ANG_UPDATE = 6         # FP32 source read + BF16 angular flux written, per update
 
 # HBM bytes per sweep launch from rocprofv3 FETCH_SIZE / WRITE_SIZE runs (scaled by a 256 MiB copy:
 # 1 FETCH_SIZE KiB = 2 KiB read, 1 WRITE_SIZE KiB = 1 KiB written), for the kernel shape the
@@ -40,9 +42,10 @@ KERNEL_SOURCES = {
               "rom_sweep_f32_8x4.hip", "rom_sweep_f32_8x8.hip", "rom_sweep_f64.hip"],
 }
 MEASURED_TRAFFIC = {  # workload: (kernel family, shape as in config, source hash, bytes per launch)
-    "c2": ("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 1, "waves_per_group": 4}, "3370bd4af69bd06d", 25594011),
-    "c1": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 1}, "3370bd4af69bd06d", 1798402),
-    "c3": ("strip", {"sweep_tile": "16x16", "band": 4}, "6c2c5693091b649e", 935117138),
+    "c2": ("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 1, "waves_per_group": 4}, "e1f013e8ca59fc4f", 25577471),
+    "c1": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "e1f013e8ca59fc4f", 1818152),
+    "c3": ("strip", {"sweep_tile": "16x16", "band": 4}, "0693cc6b5c5ce8e3", 938126849),
+    "c4": ("strip", {"sweep_tile": "8x4", "band": 4}, "0693cc6b5c5ce8e3", 446508576),
 }
 
 
@@ -282,11 +285,19 @@ def main():
     if tot_sweeps > 0:
         avg_s = tot_sweep_ms / tot_sweeps / 1e3
         upd_per_sweep = f.cells * n * wl.samples
-        achieved = FLOPS_PER_UPDATE * upd_per_sweep / avg_s / 1e12
-        peak = FP64_VECTOR_PEAK_TFLOPS if fp64 else FP32_VECTOR_PEAK_TFLOPS
-        roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak,
-                "traffic": None, "kernel": "diag_kernel" if shape[4] == 2 else "sweep_kernel",
-                "avg_launch_us": avg_s * 1e6, "updates_per_launch": upd_per_sweep}
+        kernel = "diag_kernel" if shape[4] == 2 else "sweep_kernel"
+        if wl.scattering == "iso":
+            achieved = FLOPS_PER_UPDATE * upd_per_sweep / avg_s / 1e12
+            peak = FP64_VECTOR_PEAK_TFLOPS if fp64 else FP32_VECTOR_PEAK_TFLOPS
+            roof = {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "TFLOP/s", "frac": achieved / peak}
+        else:
+            # the sweep of a dense-kernel problem streams the per-ordinate source in and the
+            # angular flux out: S (4 B) + psi (BF16, 2 B) per update
+            achieved = BYTES_PER_ANG_UPDATE * upd_per_sweep / avg_s / 1e9
+            roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS}
+        roof.update({"traffic": None, "kernel": kernel, "avg_launch_us": avg_s * 1e6,
+                     "updates_per_launch": upd_per_sweep})
     out = {
         "metric": "cell·ordinate sweep updates/s",
         "value": value,
