@@ -218,6 +218,8 @@ struct Plan {
     DevMem d_probs, d_sys, d_ws, d_lanes, d_tickets, d_slot_off, d_slot_order, d_cblocks;
     DevMem d_st, d_ss, d_q, d_src, d_phi, d_part, d_edge, d_inflow, d_prog, d_ctl, d_sysctl, d_rhist;
     DevMem d_ang, d_psi, d_Pt, d_uflags;
+    DevMem d_citems, d_cmap;  // batched contraction: per-system arguments, (system, block) map
+    int cmap_blocks = 0;
     std::vector<int64_t> pt_off;  // per system offset into d_Pt (elements)
     hipGraphExec_t gexec = nullptr;
     hipGraph_t graph = nullptr;
@@ -647,12 +649,12 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     }
 
     // lanes per group: the smallest of 16/32/64 covering the largest per-quadrant ordinate count
-    // of the batch (64 for anisotropic sources and angular-flux output, which use 64-lane groups)
+    // of the batch (64 for angular-flux output and for a single sweep with per-ordinate sources)
     struct QuadList {
         std::vector<int> idx[4];
     };
     std::vector<QuadList> ql(in.size());
-    int Lb = (aniso || psi_out) ? 64 : 16;
+    int Lb = (psi_out || (aniso && max_iter == 0)) ? 64 : 16;
     P.qcount.assign(in.size(), {0, 0, 0, 0});
     for (size_t k = 0; k < in.size(); ++k) {
         for (int l = 0; l < in[k].n; ++l) ql[k].idx[quadrant_of(in[k].dirs[3 * l], in[k].dirs[3 * l + 1])].push_back(l);
@@ -1151,22 +1153,49 @@ bool refresh_ordinates(Plan& P, const std::vector<SysInput>& in, hipStream_t s)
     return true;
 }
 
+// Contraction arguments of system k (S = sigma_s (Psi' P) + q on its [cells][npad] layout).
+ContractArgs contract_args(const Plan& P, int k)
+{
+    const SystemDev& sd = P.sys[k];
+    ContractArgs c{};
+    c.a = (const char*)P.d_psi.p + sd.ang_off * (P.fp64 ? 8 : 2);
+    c.bt = (const char*)P.d_Pt.p + P.pt_off[k] * (P.fp64 ? 8 : 2);
+    c.sigma_s = (const char*)P.d_ss.p + P.probs[sd.prob].field_off * P.esz;
+    c.q = (const char*)P.d_q.p + P.probs[sd.prob].field_off * P.esz;
+    c.out = (char*)P.d_ang.p + sd.ang_off * P.esz;
+    c.M = (int)P.handles[sd.prob]->cells;
+    c.N = c.K = P.npad_al[k];
+    c.sys_index = k;
+    c.sysctl = P.d_sysctl.as<SysCtl>();
+    return c;
+}
+
+// With several systems (an ensemble batch) all contractions of an iteration go in one launch:
+// the argument table and the block map are built once per plan (the buffers never move).
+void build_contract_batch(Plan& P)
+{
+    if (!P.aniso || P.nsys < 2) return;
+    const int kind = P.fp64 ? 2 : 0;
+    std::vector<ContractArgs> items(P.nsys);
+    std::vector<int2> map;
+    for (int k = 0; k < P.nsys; ++k) {
+        items[k] = contract_args(P, k);
+        const int nb = contract_blocks(items[k], kind);
+        if (nb < 0) throw Fail{ROM_E_DEVICE, "contraction shape not supported"};
+        for (int b = 0; b < nb; ++b) map.push_back(make_int2(k, b));
+    }
+    upload(P.d_citems, items);
+    upload(P.d_cmap, map);
+    P.cmap_blocks = (int)map.size();
+}
+
 void enqueue_iteration(Plan& P, hipStream_t s, double tol)
 {
     if (P.aniso) {
-        for (int k = 0; k < P.nsys; ++k) {
-            const SystemDev& sd = P.sys[k];
-            ContractArgs c{};
-            c.a = (const char*)P.d_psi.p + sd.ang_off * (P.fp64 ? 8 : 2);
-            c.bt = (const char*)P.d_Pt.p + P.pt_off[k] * (P.fp64 ? 8 : 2);
-            c.sigma_s = (const char*)P.d_ss.p + P.probs[sd.prob].field_off * P.esz;
-            c.q = (const char*)P.d_q.p + P.probs[sd.prob].field_off * P.esz;
-            c.out = (char*)P.d_ang.p + sd.ang_off * P.esz;
-            c.M = (int)P.handles[sd.prob]->cells;
-            c.N = c.K = P.npad_al[k];
-            c.sys_index = k;
-            c.sysctl = P.d_sysctl.as<SysCtl>();
-            HIPCHK(launch_contract(c, P.fp64 ? 2 : 0, s));
+        if (P.cmap_blocks > 0) {
+            HIPCHK(launch_contract_batch(P.d_citems.as<ContractArgs>(), P.d_cmap.as<int2>(), P.cmap_blocks, P.fp64 ? 2 : 0, s));
+        } else {
+            for (int k = 0; k < P.nsys; ++k) HIPCHK(launch_contract(contract_args(P, k), P.fp64 ? 2 : 0, s));
         }
         HIPCHK(launch_mark(P.d_ctl.as<Ctl>(), s));  // the sweep is timed from here, not from the combine
     }
@@ -1758,7 +1787,10 @@ int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opt
         if (free_shape && autotune_enabled()) autotune(in, o, smode, owner->stream());
         slot.reset(new Plan());
         build_plan(*slot, in, o, smode, o.max_iter);
-        if (aniso) build_kernel_matrices(*slot, in);
+        if (aniso) {
+            build_kernel_matrices(*slot, in);
+            build_contract_batch(*slot);
+        }
     }
     res = run_si(*slot, owner->stream(), o);
     if (res.error) return fail(owner, ROM_E_DEVICE, "sweep dependency wait timed out");

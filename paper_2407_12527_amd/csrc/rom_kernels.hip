@@ -518,7 +518,9 @@ typedef float f32x16_t __attribute__((ext_vector_type(16)));
 constexpr int GM = 128, GN = 128, GK = 32;
 constexpr int LDS_PAD = 8;  // bf16 elements of padding per LDS row (keeps 16-byte alignment)
 
-__global__ __launch_bounds__(256) void contract_bf16_kernel(ContractArgs A)
+// One GM x GN output tile (block `blk` of the `nb` blocks of this contraction); remap: spread the
+// blocks over the XCDs by contiguous runs (single launches only).
+__device__ __forceinline__ void contract_bf16_tile(const ContractArgs& A, const int blk, const int nb, const bool remap)
 {
     if (A.sysctl && A.sysctl[A.sys_index].state != 0) return;
     __shared__ __attribute__((aligned(16))) __bf16 As[GM][GK + LDS_PAD];
@@ -532,8 +534,7 @@ __global__ __launch_bounds__(256) void contract_bf16_kernel(ContractArgs A)
     // so that every XCD owns a contiguous run of logical tiles: the N/GN tiles that share one A
     // row-block then run on the same XCD and read A from HBM once.
     const int nblk_n = A.N / GN;
-    const int nb = gridDim.x;
-    const int lb = (nb % 8 == 0) ? (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8 : blockIdx.x;
+    const int lb = (remap && nb % 8 == 0) ? (blk % 8) * (nb / 8) + blk / 8 : blk;
     const int bm = lb / nblk_n, bn = lb % nblk_n;
     const int m0 = bm * GM, n0 = bn * GN;
     const __bf16* __restrict__ Ag = (const __bf16*)A.a;
@@ -600,17 +601,31 @@ __global__ __launch_bounds__(256) void contract_bf16_kernel(ContractArgs A)
     }
 }
 
+__global__ __launch_bounds__(256) void contract_bf16_kernel(ContractArgs A)
+{
+    contract_bf16_tile(A, blockIdx.x, gridDim.x, true);
+}
+
+// The contractions of several systems in one launch: block b computes tile map[b].y of
+// contraction map[b].x (an ensemble's samples each have their own small kernel matrix).
+__global__ __launch_bounds__(256) void contract_bf16_batch_kernel(const ContractArgs* __restrict__ items,
+                                                                  const int2* __restrict__ map)
+{
+    const int2 m = map[blockIdx.x];
+    contract_bf16_tile(items[m.x], m.y, 0, false);
+}
+
 // Plain tiled contraction (FP64 or FP32 operands, same precision out), 16 x 16 threads, 64 x 64
 // block tile, each thread a 4 x 4 micro-tile.
 template <typename T>
-__global__ __launch_bounds__(256) void contract_plain_kernel(ContractArgs A)
+__device__ __forceinline__ void contract_plain_tile(const ContractArgs& A, const int blk)
 {
     if (A.sysctl && A.sysctl[A.sys_index].state != 0) return;
     __shared__ T As[16][64 + 1];
     __shared__ T Bs[16][64 + 1];
     const int tx = threadIdx.x % 16, ty = threadIdx.x / 16;
     const int nblk_n = (A.N + 63) / 64;
-    const int m0 = (blockIdx.x / nblk_n) * 64, n0 = (blockIdx.x % nblk_n) * 64;
+    const int m0 = (blk / nblk_n) * 64, n0 = (blk % nblk_n) * 64;
     const T* __restrict__ Ag = (const T*)A.a;
     const T* __restrict__ Bg = (const T*)A.bt;
     T acc[4][4] = {};
@@ -650,6 +665,20 @@ __global__ __launch_bounds__(256) void contract_plain_kernel(ContractArgs A)
             if (col < A.N) out[(int64_t)row * A.N + col] = fma(ss[row], acc[u][v], q[row]);
         }
     }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void contract_plain_kernel(ContractArgs A)
+{
+    contract_plain_tile<T>(A, blockIdx.x);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void contract_plain_batch_kernel(const ContractArgs* __restrict__ items,
+                                                                   const int2* __restrict__ map)
+{
+    const int2 m = map[blockIdx.x];
+    contract_plain_tile<T>(items[m.x], m.y);
 }
 
 // FP32 angular flux -> BF16 copy (used when the sweep stored FP32 psi').
@@ -827,6 +856,21 @@ hipError_t launch_contract(const ContractArgs& a, int kind, hipStream_t s)
         else
             hipLaunchKernelGGL(contract_plain_kernel<double>, dim3(grid), dim3(256), 0, s, a);
     }
+    return hipGetLastError();
+}
+
+int contract_blocks(const ContractArgs& a, int kind)
+{
+    if (kind == 0) return (a.N % GN != 0 || a.K % GK != 0) ? -1 : ((a.M + GM - 1) / GM) * (a.N / GN);
+    return ((a.M + 63) / 64) * ((a.N + 63) / 64);
+}
+
+hipError_t launch_contract_batch(const ContractArgs* items, const int2* map, int nblocks, int kind, hipStream_t s)
+{
+    if (nblocks < 1) return hipErrorInvalidValue;
+    if (kind == 0) hipLaunchKernelGGL(contract_bf16_batch_kernel, dim3(nblocks), dim3(256), 0, s, items, map);
+    else if (kind == 1) hipLaunchKernelGGL(contract_plain_batch_kernel<float>, dim3(nblocks), dim3(256), 0, s, items, map);
+    else hipLaunchKernelGGL(contract_plain_batch_kernel<double>, dim3(nblocks), dim3(256), 0, s, items, map);
     return hipGetLastError();
 }
 

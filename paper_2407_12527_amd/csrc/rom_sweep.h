@@ -501,7 +501,9 @@ hipError_t launch_sweep_t(const SweepArgs& a, int grid, hipStream_t s)
 }
 
 // Dispatch over scheme, source kind, angular-flux output and lane-group size for one tile shape.
-// Anisotropic sources and angular-flux output always use 64-lane groups.
+// Angular-flux output uses 64-lane groups, except in source iteration with a dense kernel (per-
+// ordinate sources in, BF16 / FP64 angular flux out), where a batch of small ordinate sets packs
+// 16 or 32 lanes per system.
 template <typename T, int TX, int TY>
 hipError_t launch_sweep_tile(const SweepArgs& a, int grid, bool dd, bool ang, int psi, int L, int mom, hipStream_t s)
 {
@@ -514,6 +516,12 @@ hipError_t launch_sweep_tile(const SweepArgs& a, int grid, bool dd, bool ang, in
     }
     if (mom != 1) return hipErrorInvalidValue;
     if (ang || psi) {
+        constexpr int PSIV = sizeof(T) == 8 ? 1 : 2;  // the iteration's angular-flux output
+        if (ang && psi == PSIV && L != 64) {
+            if (L == 32) return dd ? launch_sweep_t<T, TX, TY, true, true, PSIV, 32>(a, grid, s) : launch_sweep_t<T, TX, TY, false, true, PSIV, 32>(a, grid, s);
+            if (L == 16) return dd ? launch_sweep_t<T, TX, TY, true, true, PSIV, 16>(a, grid, s) : launch_sweep_t<T, TX, TY, false, true, PSIV, 16>(a, grid, s);
+            return hipErrorInvalidValue;
+        }
         if (L != 64) return hipErrorInvalidValue;
         if (ang) {
             if (psi == 2) return dd ? launch_sweep_t<T, TX, TY, true, true, 2, 64>(a, grid, s) : launch_sweep_t<T, TX, TY, false, true, 2, 64>(a, grid, s);
