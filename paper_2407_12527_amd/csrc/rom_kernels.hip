@@ -511,12 +511,17 @@ __global__ void finish_var_kernel(const double* m2, double* var, int64_t cells, 
 // S[m][n] = sigma_s[m] * sum_k A[m][k] Bt[n][k] + q[m], A = Psi' [cells][npad], Bt = P^T.
 //
 // BF16 MFMA version: 256 threads = 4 waves in a 2 x 2 arrangement, block tile 128 x 128, K step
-// 32 staged in LDS; each wave owns 64 x 64 = 2 x 2 tiles of v_mfma_f32_32x32x16_bf16.
+// 64 staged in LDS; each wave owns 64 x 64 = 2 x 2 tiles of v_mfma_f32_32x32x16_bf16.  The next
+// K step's tiles are loaded into registers while the matrix cores work on the current one, so
+// the global-load latency overlaps the MFMA of the step before it.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
-constexpr int GM = 128, GN = 128, GK = 32;
+constexpr int GM = 128, GN = 128, GK = 64;
 constexpr int LDS_PAD = 8;  // bf16 elements of padding per LDS row (keeps 16-byte alignment)
+constexpr int kSegs = GK / 8;               // 16-byte segments of one tile row
+constexpr int kRowStep = 256 / kSegs;      // tile rows moved by the block per piece
+constexpr int kStage = GM / kRowStep;      // 16-byte pieces of one operand tile per thread
 
 // One GM x GN output tile (block `blk` of the `nb` blocks of this contraction); remap: spread the
 // blocks over the XCDs by contiguous runs (single launches only).
@@ -525,20 +530,25 @@ __device__ __forceinline__ void contract_bf16_tile(const ContractArgs& A, const 
     if (A.sysctl && A.sysctl[A.sys_index].state != 0) return;
     __shared__ __attribute__((aligned(16))) __bf16 As[GM][GK + LDS_PAD];
     __shared__ __attribute__((aligned(16))) __bf16 Bs[GN][GK + LDS_PAD];
+    __shared__ float ss_q[2][GM];  // sigma_s and q of the block's rows, for the epilogue
     const int tid = threadIdx.x;
     const int wave = tid / 64, lane = tid % 64;
     const int wm = wave / 2, wn = wave % 2;
-    // XCD-aware block order is left to the dispatcher; blocks walk N fastest so that one A tile
-    // (the large operand) is reused from L2 by the N/GN blocks that follow it.
     // Workgroups are dispatched round-robin over the 8 XCDs, each with its own L2.  Renumber them
     // so that every XCD owns a contiguous run of logical tiles: the N/GN tiles that share one A
-    // row-block then run on the same XCD and read A from HBM once.
+    // row-block (the large operand) then run on the same XCD and read A from HBM once.
     const int nblk_n = A.N / GN;
     const int lb = (remap && nb % 8 == 0) ? (blk % 8) * (nb / 8) + blk / 8 : blk;
     const int bm = lb / nblk_n, bn = lb % nblk_n;
     const int m0 = bm * GM, n0 = bn * GN;
     const __bf16* __restrict__ Ag = (const __bf16*)A.a;
     const __bf16* __restrict__ Bg = (const __bf16*)A.bt;
+    if (tid < 2 * GM) {
+        // rows past M take row M - 1's values; their results are never stored.  The first barrier
+        // of the K loop orders these stores before the epilogue's reads.
+        const int r = min(m0 + tid % GM, A.M - 1);
+        ss_q[tid / GM][tid % GM] = tid < GM ? ((const float*)A.sigma_s)[r] : ((const float*)A.q)[r];
+    }
 
     f32x16_t acc[2][2];
 #pragma unroll
@@ -548,20 +558,34 @@ __device__ __forceinline__ void contract_bf16_tile(const ContractArgs& A, const 
 #pragma unroll
             for (int e = 0; e < 16; ++e) acc[x][y][e] = 0.0f;
 
-    // global -> LDS: each tile is 128 rows x 32 bf16 = 128 x 64 B; 256 threads x 2 x 16 B
+    // global -> registers: each tile is 128 rows x GK bf16, 256 threads x kStage x 16 B; thread tid
+    // moves rows tid / kSegs + kRowStep h, 16-byte segment tid % kSegs.  Rows of A past M read row
+    // M - 1 (in bounds) and their results are never stored.
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 ra[kStage], rb[kStage];
+    const int row0 = tid / kSegs, seg = tid % kSegs;
+    auto a_at = [&](const int h) { return Ag + (int64_t)min(m0 + row0 + kRowStep * h, A.M - 1) * A.K + seg * 8; };
+    const __bf16* __restrict__ pb = Bg + (int64_t)(n0 + row0) * A.K + seg * 8;
+    const int64_t sb = kRowStep * (int64_t)A.K;
+#pragma unroll
+    for (int h = 0; h < kStage; ++h) {
+        ra[h] = *(const u32x4*)a_at(h);
+        rb[h] = *(const u32x4*)(pb + h * sb);
+    }
     for (int k0 = 0; k0 < A.K; k0 += GK) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int idx = tid + h * 256;  // 0..511
-            const int row = idx / 4, seg = idx % 4;
-            const int am = m0 + row;
-            uint4 va = make_uint4(0, 0, 0, 0);
-            if (am < A.M) va = *(const uint4*)(Ag + (int64_t)am * A.K + k0 + seg * 8);
-            *(uint4*)&As[row][seg * 8] = va;
-            const uint4 vb = *(const uint4*)(Bg + (int64_t)(n0 + row) * A.K + k0 + seg * 8);
-            *(uint4*)&Bs[row][seg * 8] = vb;
+        for (int h = 0; h < kStage; ++h) {
+            *(u32x4*)&As[row0 + kRowStep * h][seg * 8] = ra[h];
+            *(u32x4*)&Bs[row0 + kRowStep * h][seg * 8] = rb[h];
         }
         __syncthreads();
+        if (k0 + GK < A.K) {
+#pragma unroll
+            for (int h = 0; h < kStage; ++h) {
+                ra[h] = *(const u32x4*)(a_at(h) + k0 + GK);
+                rb[h] = *(const u32x4*)(pb + h * sb + k0 + GK);
+            }
+        }
 #pragma unroll
         for (int kk = 0; kk < GK; kk += 16) {
             bf16x8_t af[2], bfr[2];
@@ -584,8 +608,6 @@ __device__ __forceinline__ void contract_bf16_tile(const ContractArgs& A, const 
         __syncthreads();
     }
     // epilogue: lane holds column (lane % 32) and rows 8*(e/4) + 4*(lane/32) + e%4 of each tile
-    const float* __restrict__ ss = (const float*)A.sigma_s;
-    const float* __restrict__ q = (const float*)A.q;
     float* __restrict__ out = (float*)A.out;
 #pragma unroll
     for (int x = 0; x < 2; ++x) {
@@ -594,8 +616,9 @@ __device__ __forceinline__ void contract_bf16_tile(const ContractArgs& A, const 
             const int col = n0 + wn * 64 + y * 32 + (lane % 32);
 #pragma unroll
             for (int e = 0; e < 16; ++e) {
-                const int row = m0 + wm * 64 + x * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
-                if (row < A.M) out[(int64_t)row * A.N + col] = fmaf(ss[row], acc[x][y][e], q[row]);
+                const int rl = wm * 64 + x * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+                const int row = m0 + rl;
+                if (row < A.M) out[(int64_t)row * A.N + col] = fmaf(ss_q[0][rl], acc[x][y][e], ss_q[1][rl]);
             }
         }
     }
