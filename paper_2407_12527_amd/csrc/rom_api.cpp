@@ -195,6 +195,7 @@ struct Plan {
     std::vector<int2> tickets;
     std::vector<int64_t> slot_off;
     std::vector<int32_t> slot_order;
+    std::vector<int64_t> slot_off_ord;  // slot_off in summation order
     std::vector<int2> cblocks;
     std::vector<std::vector<int>> user_of;  // per system: internal index -> caller index (-1 pad)
     std::vector<int> sys_n;                 // per system: real ordinate count
@@ -215,7 +216,7 @@ struct Plan {
     std::vector<DiagTaskDev> dtasks;
     DevMem d_dtasks;
 
-    DevMem d_probs, d_sys, d_ws, d_lanes, d_tickets, d_slot_off, d_slot_order, d_cblocks;
+    DevMem d_probs, d_sys, d_ws, d_lanes, d_tickets, d_slot_off, d_slot_order, d_slot_off_ord, d_cblocks;
     DevMem d_st, d_ss, d_q, d_src, d_phi, d_part, d_edge, d_inflow, d_prog, d_ctl, d_sysctl, d_rhist;
     DevMem d_ang, d_psi, d_Pt, d_uflags;
     DevMem d_citems, d_cmap;  // batched contraction: per-system arguments, (system, block) map
@@ -304,6 +305,7 @@ struct Plan {
         c.probs = d_probs.as<ProblemDev>();
         c.slot_order = d_slot_order.as<int32_t>();
         c.slot_off = d_slot_off.as<int64_t>();
+        c.slot_off_ord = d_slot_off_ord.as<int64_t>();
         c.blocks = d_cblocks.as<int2>();
         c.cells_per_block = cells_per_block;
         c.many_cpt = many_cpt;
@@ -924,6 +926,9 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     upload(P.d_tickets, P.tickets);
     upload(P.d_slot_off, P.slot_off);
     upload(P.d_slot_order, P.slot_order);
+    P.slot_off_ord.resize(P.slot_order.size());
+    for (size_t i = 0; i < P.slot_order.size(); ++i) P.slot_off_ord[i] = P.slot_off[P.slot_order[i]];
+    upload(P.d_slot_off_ord, P.slot_off_ord);
     upload(P.d_cblocks, P.cblocks);
     upload(P.d_uflags, uflags);
     upload(P.d_dtasks, P.dtasks);

@@ -60,6 +60,7 @@ struct CombineArgs {
     const ProblemDev* probs;
     const int32_t* slot_order;
     const int64_t* slot_off;
+    const int64_t* slot_off_ord;  // slot_off[slot_order[i]]: offsets in summation order
     const int2* blocks;        // (system, first cell) per block
     int32_t cells_per_block;
     int32_t many_cpt;          // 0: one wave sums all slots of 4 cells per thread; 1, 2, 4, 8: the

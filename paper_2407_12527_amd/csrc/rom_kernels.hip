@@ -216,10 +216,7 @@ __global__ __launch_bounds__(256) void combine_many_kernel(CombineArgs A)
     combine_tail(A, run, s, dmax, pmax);
 }
 
-// Many-slot combine with vector loads: a block owns 64 lanes x 16 bytes of consecutive cells
-// (256 FP32 / 128 FP64 cells); its four waves take every fourth slot, each lane keeping U
-// 16-byte loads in flight in U independent accumulators, folded in a fixed order, then the waves'
-// totals are added as ((w0 + w1) + (w2 + w3)) -- deterministic for a given slot count.
+// 16-byte vector of T
 template <typename T>
 struct Vec16;
 template <>
@@ -231,12 +228,20 @@ struct Vec16<double> {
     using type = double2;
 };
 
+// Many-slot combine with 16-byte loads: a block owns 64 * 16 bytes of consecutive cells (256
+// FP32 / 128 FP64 cells), each lane 16 bytes of them; the block's four waves split the system's
+// slots (wave w takes slots w, w + 4, ...) and a lane keeps up to 16 slot loads in flight in 16
+// independent accumulators, so a system of up to 64 slots is read in one round trip.  phi,
+// sigma_s and q of the cell a thread updates are loaded before the slots, and the slot offsets
+// come from a table already in summation order, so no load waits on another.  Each wave folds
+// its accumulators in a fixed tree and the wave totals are added as ((w0 + w1) + (w2 + w3)):
+// deterministic for a given slot count.
 template <typename T>
 __global__ __launch_bounds__(256) void combine_vec_kernel(CombineArgs A)
 {
     using V4 = typename Vec16<T>::type;
     constexpr int V = 16 / sizeof(T);
-    constexpr int U = 8;
+    constexpr int U = 16;
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (A.mode == 0 && A.ctl->active == 0) return;
     const int2 blk = A.blocks[blockIdx.x];
@@ -247,11 +252,21 @@ __global__ __launch_bounds__(256) void combine_vec_kernel(CombineArgs A)
     const bool run = A.mode == 1 || A.sysctl[s].state == 0;
     __shared__ T wsum[4][64 * V];
     double dmax = 0.0, pmax = 0.0;
+    // the cell this thread updates (64 * V <= 256 cells per block)
+    const int ucell = blk.y + tid;
+    const bool upd = run && tid < 64 * V && ucell < cells;
+    T* __restrict__ phi = (T*)A.phi + SD.phi_off;
+    T* __restrict__ src = (T*)A.src + SD.src_off;
+    T old = T(0), ssv = T(0), qv = T(0);
+    if (upd) {
+        old = phi[ucell];
+        ssv = ((const T*)A.sigma_s + P.field_off)[ucell];
+        qv = ((const T*)A.q + P.field_off)[ucell];
+    }
     if (run) {
         const T* __restrict__ part = (const T*)A.part;
         const int ns = SD.nslots;
-        const int64_t* __restrict__ soff = A.slot_off;
-        const int32_t* __restrict__ sord = A.slot_order + SD.slot_first;
+        const int64_t* __restrict__ soff = A.slot_off_ord + SD.slot_first;
         const int c0 = blk.y + lane * V;
         const bool in = c0 < cells;  // cells is a multiple of V: a lane's V cells are all in or all out
         V4 acc[U];
@@ -261,33 +276,27 @@ __global__ __launch_bounds__(256) void combine_vec_kernel(CombineArgs A)
         for (; k + 4 * (U - 1) < ns; k += 4 * U) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (in) acc[u] += *(const V4*)(part + soff[sord[k + 4 * u]] + c0);
+                if (in) acc[u] += *(const V4*)(part + soff[k + 4 * u] + c0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (in && k + 4 * u < ns) acc[u] += *(const V4*)(part + soff[sord[k + 4 * u]] + c0);
-        const V4 tot = ((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7]));
-        const T* tv = (const T*)&tot;
+            if (in && k + 4 * u < ns) acc[u] += *(const V4*)(part + soff[k + 4 * u] + c0);
+#pragma unroll
+        for (int h = U / 2; h > 0; h /= 2)
+#pragma unroll
+            for (int u = 0; u < h; ++u) acc[u] += acc[u + h];
+        const T* tv = (const T*)&acc[0];
 #pragma unroll
         for (int i = 0; i < V; ++i) wsum[wave][lane * V + i] = tv[i];
     }
     __syncthreads();
-    if (run) {
-        T* __restrict__ phi = (T*)A.phi + SD.phi_off;
-        T* __restrict__ src = (T*)A.src + SD.src_off;
-        const T* __restrict__ ss = (const T*)A.sigma_s + P.field_off;
-        const T* __restrict__ q = (const T*)A.q + P.field_off;
-        for (int e = tid; e < 64 * V; e += 256) {
-            const int cell = blk.y + e;
-            if (cell < cells) {
-                const T v = (wsum[0][e] + wsum[1][e]) + (wsum[2][e] + wsum[3][e]);
-                const T old = phi[cell];
-                dmax = fmax(dmax, fabs((double)v - (double)old));
-                pmax = fmax(pmax, fabs((double)v));
-                phi[cell] = v;
-                src[cell] = fma(ss[cell], v, q[cell]);
-            }
-        }
+    if (upd) {
+        const int e = tid;
+        const T v = (wsum[0][e] + wsum[1][e]) + (wsum[2][e] + wsum[3][e]);
+        dmax = fabs((double)v - (double)old);
+        pmax = fabs((double)v);
+        phi[ucell] = v;
+        src[ucell] = fma(ssv, v, qv);
     }
     combine_tail(A, run, s, dmax, pmax);
 }
