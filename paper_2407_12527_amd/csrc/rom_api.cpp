@@ -1281,17 +1281,20 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
         P.graph_tol = tol;
     }
     Ctl ctl{};
+    SolveResult r;
+    r.sc.resize(P.nsys);
     int launched = 0;
     for (;;) {
         HIPCHK(hipGraphLaunch(P.gexec, s));
         launched += K;
+        // the control block and the per-system states come back behind one synchronization
         HIPCHK(hipMemcpyAsync(&ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(r.sc.data(), P.d_sysctl.p, P.nsys * sizeof(SysCtl), hipMemcpyDeviceToHost, s));
         HIPCHK(hipStreamSynchronize(s));
         if (ctl.error || ctl.active == 0 || launched >= P.max_iter + K) break;
     }
     HIPCHK(hipEventRecord(e1, s));
     HIPCHK(hipEventSynchronize(e1));
-    SolveResult r;
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     r.ms = ms;
@@ -1300,8 +1303,6 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     r.error = ctl.error != 0;
     r.sweep_ms = (double)ctl.sweep_ticks / wallclock_khz();
     r.sweeps = ctl.sweeps;
-    r.sc.resize(P.nsys);
-    HIPCHK(hipMemcpy(r.sc.data(), P.d_sysctl.p, P.nsys * sizeof(SysCtl), hipMemcpyDeviceToHost));
     int most = 0;
     for (const SysCtl& c : r.sc) most = std::max(most, c.iter);
     P.last_iters = most;
