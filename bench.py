@@ -167,12 +167,12 @@ def bench_batch(a, wl, R, torch):
     tile = tuple(int(v) for v in a.tile.lower().split("x"))
     opts = R.si_opts(tol=wl.tol, max_iter=wl.max_iter, tile=tile, band=a.band, **kernel_opts(a, R))
     for _ in range(a.warmup):
-        R.solve_batch(hs, opts)
+        R.solve_batch(hs, opts, download=False)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     upd, sweep_ms, sweeps, iters, shape = 0, 0.0, 0, 0, [0, 0, 0, 0, 0]
     for _ in range(a.steps):
-        _, stats, rc = R.solve_batch(hs, opts)
+        _, stats, rc = R.solve_batch(hs, opts, download=False)  # fluxes stay in HBM
         if rc != 0:
             raise RuntimeError(f"batch did not converge (status {rc})")
         upd += sum(s.updates for s in stats)

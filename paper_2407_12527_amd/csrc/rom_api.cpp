@@ -1242,11 +1242,10 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     for (auto& sd : P.sys) phi_total = std::max<int64_t>(phi_total, sd.phi_off + P.handles[sd.prob]->cells);
     HIPCHK(launch_fill(P.d_phi.p, phi_total, P.fp64, 0.0, s));
     if (P.nmom == 4) HIPCHK(launch_fill(P.src_ptr(), P.src_len, P.fp64, 0.0, s));  // S1 = S2 = 0
-    for (auto& sd : P.sys) {
-        const int64_t cells = P.handles[sd.prob]->cells;
-        HIPCHK(hipMemcpyAsync(P.src_ptr() + sd.src_off * P.esz, (char*)P.d_q.p + P.probs[sd.prob].field_off * P.esz,
-                              cells * P.esz, hipMemcpyDeviceToDevice, s));
-    }
+    int64_t max_cells = 0;
+    for (auto& sd : P.sys) max_cells = std::max<int64_t>(max_cells, P.handles[sd.prob]->cells);
+    HIPCHK(launch_init_source(P.d_sys.as<SystemDev>(), P.d_probs.as<ProblemDev>(), P.nsys, max_cells, P.fp64, P.d_q.p,
+                              P.src_ptr(), s));
     if (P.aniso) {
         int64_t tot = 0;
         for (int k = 0; k < P.nsys; ++k) tot = std::max<int64_t>(tot, P.sys[k].ang_off + P.handles[P.sys[k].prob]->cells * (int64_t)P.npad_al[k]);

@@ -847,6 +847,33 @@ hipError_t launch_reset_systems(SysCtl* sc, int nsys, Ctl* ctl, hipStream_t s)
     return hipGetLastError();
 }
 
+// First source of every system: S = q (phi starts at 0), one launch for all systems;
+// grid.y strides over the systems, grid.x over each system's cells.
+template <typename T>
+__global__ void init_source_kernel(const SystemDev* __restrict__ sys, const ProblemDev* __restrict__ probs, int nsys,
+                                   const T* __restrict__ q, T* __restrict__ src)
+{
+    for (int k = blockIdx.y; k < nsys; k += gridDim.y) {
+        const SystemDev& sd = sys[k];
+        const ProblemDev& pd = probs[sd.prob];
+        const int64_t cells = (int64_t)pd.nx * pd.ny;
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x)
+            src[sd.src_off + c] = q[pd.field_off + c];
+    }
+}
+
+hipError_t launch_init_source(const SystemDev* sys, const ProblemDev* probs, int nsys, int64_t max_cells, bool fp64,
+                              const void* q, void* src, hipStream_t s)
+{
+    if (nsys <= 0 || max_cells <= 0) return hipSuccess;
+    const dim3 grid((unsigned)std::min<int64_t>((max_cells + 255) / 256, 1024), (unsigned)std::min(nsys, 65535));
+    if (fp64)
+        hipLaunchKernelGGL(init_source_kernel<double>, grid, dim3(256), 0, s, sys, probs, nsys, (const double*)q, (double*)src);
+    else
+        hipLaunchKernelGGL(init_source_kernel<float>, grid, dim3(256), 0, s, sys, probs, nsys, (const float*)q, (float*)src);
+    return hipGetLastError();
+}
+
 hipError_t launch_fill(void* p, int64_t n, bool fp64, double v, hipStream_t s)
 {
     const int nb = (int)std::min<int64_t>((n + 255) / 256, 4096);

@@ -395,11 +395,13 @@ class Handle:
         return out
 
 
-def solve_batch(handles, opts=None):
+def solve_batch(handles, opts=None, download=True):
+    """rom_solve_batch over the handles; download=False leaves the fluxes on the device
+    (outs is then a list of None)."""
     k = len(handles)
     hs = (C.c_void_p * k)(*[h.h for h in handles])
-    outs = [np.empty(h.cells) for h in handles]
-    ps = (C.c_void_p * k)(*[o.ctypes.data for o in outs])
+    outs = [np.empty(h.cells) for h in handles] if download else [None] * k
+    ps = (C.c_void_p * k)(*[o.ctypes.data for o in outs]) if download else None
     stats = (rom_si_stats * k)()
     rc = lib().rom_solve_batch(hs, k, C.byref(opts) if opts else None, ps, stats)
     if rc < 0:
