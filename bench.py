@@ -46,6 +46,7 @@ MEASURED_TRAFFIC = {  # workload: (kernel family, shape as in config, source has
     "c1": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "e1f013e8ca59fc4f", 1818152),
     "c3": ("strip", {"sweep_tile": "16x16", "band": 4}, "77c60af2502977e7", 938147087),
     "c4": ("strip", {"sweep_tile": "8x4", "band": 4}, "77c60af2502977e7", 446438498),
+    "c5": ("strip", {"sweep_tile": "16x16", "band": 4}, "77c60af2502977e7", 2725930859),
 }
 
 
@@ -194,6 +195,7 @@ def bench_batch(a, wl, R, torch):
            "roofline": {"bound": "alu", "achieved": achieved, "peak": FP32_VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                         "frac": achieved / FP32_VECTOR_PEAK_TFLOPS, "traffic": None, "kernel": "sweep_kernel",
                         "avg_launch_us": avg_s * 1e6, "updates_per_launch": upd / max(sweeps, 1)}}
+    out["roofline"]["traffic"] = measured_traffic("c5", out["config"])
     if not a.no_cpu:
         out["cpu_baseline"] = cpu_baseline_batch(wl, a.cpu_seconds)
     print(json.dumps(out), flush=True)
