@@ -41,12 +41,13 @@ KERNEL_SOURCES = {
     "strip": ["rom_common.h", "rom_device.h", "rom_sweep.h", "rom_sweep_f32_16x16.hip", "rom_sweep_f32_16x8.hip",
               "rom_sweep_f32_8x4.hip", "rom_sweep_f32_8x8.hip", "rom_sweep_f64.hip"],
 }
-MEASURED_TRAFFIC = {  # workload: (kernel family, shape as in config, source hash, bytes per launch)
-    "c2": ("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 1, "waves_per_group": 4}, "e1f013e8ca59fc4f", 25577471),
-    "c1": ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "e1f013e8ca59fc4f", 1818152),
-    "c3": ("strip", {"sweep_tile": "16x16", "band": 4}, "77c60af2502977e7", 938147087),
-    "c4": ("strip", {"sweep_tile": "8x4", "band": 4}, "77c60af2502977e7", 446438498),
-    "c5": ("strip", {"sweep_tile": "16x16", "band": 4}, "77c60af2502977e7", 2725930859),
+MEASURED_TRAFFIC = {  # workload: [(kernel family, shape as in config, source hash, bytes per launch), ...]
+    "c2": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 1, "waves_per_group": 4}, "e1f013e8ca59fc4f", 25577471),
+           ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "e1f013e8ca59fc4f", 38971236)],
+    "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "e1f013e8ca59fc4f", 1818152)],
+    "c3": [("strip", {"sweep_tile": "16x16", "band": 4}, "77c60af2502977e7", 938147087)],
+    "c4": [("strip", {"sweep_tile": "8x4", "band": 4}, "77c60af2502977e7", 446438498)],
+    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "77c60af2502977e7", 2725930859)],
 }
 
 
@@ -60,13 +61,12 @@ def kernel_hash(family):
 
 
 def measured_traffic(workload, config):
-    ent = MEASURED_TRAFFIC.get(workload)
-    if not ent:
-        return None
-    family, shape, digest, nbytes = ent
-    if config.get("sweep_kernel") != family or any(config.get(k) != v for k, v in shape.items()):
-        return None
-    return nbytes if kernel_hash(family) == digest else None
+    """HBM bytes per launch of the profiled kernel, if this run used a profiled shape and the
+    kernel sources still hash to the profiled ones (else None)."""
+    for family, shape, digest, nbytes in MEASURED_TRAFFIC.get(workload, []):
+        if config.get("sweep_kernel") == family and all(config.get(k) == v for k, v in shape.items()):
+            return nbytes if kernel_hash(family) == digest else None
+    return None
 
 
 DESCR = {

@@ -284,3 +284,26 @@ def test_batch_uneven_problems(R, orc):
     assert rc == 0
     for o_, r_ in zip(outs, refs):
         assert nrm(o_, r_) < 1e-5
+
+
+def test_batch_without_download_then_with(R, orc):
+    """A batch solve that leaves the fluxes on the device reports the same iteration counts as
+    one that downloads them, and the following downloading solve (plan reused, first sources set
+    again by the one-launch initialization) still matches the oracle."""
+    wl = RI.c5(count=4, sides=(16, 32), m_range=(4, 12))
+    hs, refs = [], []
+    for k, f in enumerate(wl.fields):
+        h, p = both(R, orc, f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+        nz, nt = orc.stratified_spec(wl.n_ord[k])
+        d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, nz, nt, seed=wl.problem_seed(k))
+        h.set_ordinates(d, w)
+        hs.append(h)
+        refs.append(orc.source_iterate(p, d, w, None, tol=1e-6))
+    o = R.si_opts(tol=1e-6)
+    outs0, st0, rc0 = R.solve_batch(hs, o, download=False)
+    assert rc0 == 0 and outs0 == [None] * len(hs)
+    outs1, st1, rc1 = R.solve_batch(hs, o)
+    assert rc1 == 0
+    for a, b, o_, r_ in zip(st0, st1, outs1, refs):
+        assert a.iters == b.iters and abs(b.iters - r_["iters"]) <= 1
+        assert nrm(o_, r_["phi"]) < 1e-5
