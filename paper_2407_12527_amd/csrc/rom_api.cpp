@@ -901,7 +901,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         bool aligned = true;
         for (auto& si : in) aligned = aligned && si.h->cells % V == 0;
         if (maxslots > 8 && P.nmom == 1 && aligned && vec_combine_enabled()) {
-            P.vec = 1;
+            P.vec = maxslots > 64 ? 3 : 1;  // 8 waves per block above 64 slots
             P.cells_per_block = 64 * V;
         } else if (P.nmom == 1 && aligned && vec_combine_enabled()) {
             P.vec = 2;  // few slots: one thread sums all slots of 16 bytes of cells, 4 tiles

@@ -73,7 +73,8 @@ struct CombineArgs {
     int32_t mom_r;             // linear kernel: phi~ comes from plane 3 (else phi~ = phi)
     int32_t vec;               // 16-byte loads (every system's cell count a multiple of 16 B /
                                // sizeof(T)): 1 many slots, tiles of 64 * 16 B of cells split over
-                               // the block's waves by slot; 2 at most 8 slots, 4 tiles of 256 * 16 B
+                               // the block's 4 waves by slot (3: 8 waves, above 64 slots); 2 at
+                               // most 8 slots, 4 tiles of 256 * 16 B
     double tol;
     const void* part;
     void* phi;

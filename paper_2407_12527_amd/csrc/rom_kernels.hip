@@ -57,15 +57,20 @@ __device__ __forceinline__ void combine_tail(const CombineArgs& A, bool run, int
         dmax = fmax(dmax, __shfl_xor(dmax, off, 64));
         pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
     }
-    __shared__ double sd[4], sp[4];
+    __shared__ double sd[8], sp[8];  // one per wave (blocks of up to 8 waves)
     if ((tid & 63) == 0) {
         sd[tid >> 6] = dmax;
         sp[tid >> 6] = pmax;
     }
     __syncthreads();
     if (tid == 0) {
-        dmax = fmax(fmax(sd[0], sd[1]), fmax(sd[2], sd[3]));
-        pmax = fmax(fmax(sp[0], sp[1]), fmax(sp[2], sp[3]));
+        const int nw = (int)blockDim.x >> 6;
+        for (int k = 1; k < nw; ++k) {
+            sd[0] = fmax(sd[0], sd[k]);
+            sp[0] = fmax(sp[0], sp[k]);
+        }
+        dmax = sd[0];
+        pmax = sp[0];
         if (run && A.mode == 0) {
             atomicMax(&A.sysctl[s].dmax_bits, dbits(dmax));  // non-negative doubles order as integers
             atomicMax(&A.sysctl[s].pmax_bits, dbits(pmax));
@@ -229,19 +234,20 @@ struct Vec16<double> {
 };
 
 // Many-slot combine with 16-byte loads: a block owns 64 * 16 bytes of consecutive cells (256
-// FP32 / 128 FP64 cells), each lane 16 bytes of them; the block's four waves split the system's
-// slots (wave w takes slots w, w + 4, ...) and a lane keeps up to 16 slot loads in flight in 16
-// independent accumulators, so a system of up to 64 slots is read in one round trip.  phi,
-// sigma_s and q of the cell a thread updates are loaded before the slots, and the slot offsets
-// come from a table already in summation order, so no load waits on another.  Each wave folds
-// its accumulators in a fixed tree and the wave totals are added as ((w0 + w1) + (w2 + w3)):
-// deterministic for a given slot count.
-template <typename T>
-__global__ __launch_bounds__(256) void combine_vec_kernel(CombineArgs A)
+// FP32 / 128 FP64 cells), each lane 16 bytes of them; the block's NW waves (4 or 8) split the
+// system's slots (wave w takes slots w, w + NW, ...) and a lane keeps up to 16 slot loads in
+// flight in 16 independent accumulators, so a system of up to 16 NW slots is read in one round
+// trip.  phi, sigma_s and q of the cell a thread updates are loaded before the slots, and the
+// slot offsets come from a table already in summation order, so no load waits on another.  Each
+// wave folds its accumulators in a fixed tree and the wave totals are added pairwise in a fixed
+// tree: deterministic for a given slot count and NW.
+template <typename T, int NW>
+__global__ __launch_bounds__(64 * NW) void combine_vec_kernel(CombineArgs A)
 {
     using V4 = typename Vec16<T>::type;
     constexpr int V = 16 / sizeof(T);
     constexpr int U = 16;
+    static_assert(NW == 4 || NW == 8, "4 or 8 waves");
     const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
     if (A.mode == 0 && A.ctl->active == 0) return;
     const int2 blk = A.blocks[blockIdx.x];
@@ -250,7 +256,7 @@ __global__ __launch_bounds__(256) void combine_vec_kernel(CombineArgs A)
     const ProblemDev& P = A.probs[SD.prob];
     const int cells = P.nx * P.ny;
     const bool run = A.mode == 1 || A.sysctl[s].state == 0;
-    __shared__ T wsum[4][64 * V];
+    __shared__ T wsum[NW][64 * V];
     double dmax = 0.0, pmax = 0.0;
     // the cell this thread updates (64 * V <= 256 cells per block)
     const int ucell = blk.y + tid;
@@ -273,14 +279,14 @@ __global__ __launch_bounds__(256) void combine_vec_kernel(CombineArgs A)
 #pragma unroll
         for (int u = 0; u < U; ++u) acc[u] = V4{};
         int k = wave;
-        for (; k + 4 * (U - 1) < ns; k += 4 * U) {
+        for (; k + NW * (U - 1) < ns; k += NW * U) {
 #pragma unroll
             for (int u = 0; u < U; ++u)
-                if (in) acc[u] += *(const V4*)(part + soff[k + 4 * u] + c0);
+                if (in) acc[u] += *(const V4*)(part + soff[k + NW * u] + c0);
         }
 #pragma unroll
         for (int u = 0; u < U; ++u)
-            if (in && k + 4 * u < ns) acc[u] += *(const V4*)(part + soff[k + 4 * u] + c0);
+            if (in && k + NW * u < ns) acc[u] += *(const V4*)(part + soff[k + NW * u] + c0);
 #pragma unroll
         for (int h = U / 2; h > 0; h /= 2)
 #pragma unroll
@@ -292,7 +298,8 @@ __global__ __launch_bounds__(256) void combine_vec_kernel(CombineArgs A)
     __syncthreads();
     if (upd) {
         const int e = tid;
-        const T v = (wsum[0][e] + wsum[1][e]) + (wsum[2][e] + wsum[3][e]);
+        T v = (wsum[0][e] + wsum[1][e]) + (wsum[2][e] + wsum[3][e]);
+        if constexpr (NW == 8) v += (wsum[4][e] + wsum[5][e]) + (wsum[6][e] + wsum[7][e]);
         dmax = fabs((double)v - (double)old);
         pmax = fabs((double)v);
         phi[ucell] = v;
@@ -803,12 +810,19 @@ hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStrea
         else hipLaunchKernelGGL(combine_vec_few_kernel<float>, dim3(nblocks), dim3(256), 0, s, a);
         return hipGetLastError();
     }
-    if (a.vec) {
+    if (a.vec == 1 || a.vec == 3) {
+        // 4 waves per block; 8 for systems of more than 64 slots
         if (a.cells_per_block != 64 * (fp64 ? 2 : 4)) return hipErrorInvalidValue;
-        if (fp64) hipLaunchKernelGGL(combine_vec_kernel<double>, dim3(nblocks), dim3(256), 0, s, a);
-        else hipLaunchKernelGGL(combine_vec_kernel<float>, dim3(nblocks), dim3(256), 0, s, a);
+        if (a.vec == 3) {
+            if (fp64) hipLaunchKernelGGL((combine_vec_kernel<double, 8>), dim3(nblocks), dim3(512), 0, s, a);
+            else hipLaunchKernelGGL((combine_vec_kernel<float, 8>), dim3(nblocks), dim3(512), 0, s, a);
+        } else {
+            if (fp64) hipLaunchKernelGGL((combine_vec_kernel<double, 4>), dim3(nblocks), dim3(256), 0, s, a);
+            else hipLaunchKernelGGL((combine_vec_kernel<float, 4>), dim3(nblocks), dim3(256), 0, s, a);
+        }
         return hipGetLastError();
     }
+    if (a.vec) return hipErrorInvalidValue;
     if (a.many_cpt > 0) {
         // block tiles of 64 * many_cpt cells (cells_per_block must match)
         if (a.cells_per_block != 64 * a.many_cpt) return hipErrorInvalidValue;
