@@ -166,6 +166,25 @@ def test_si_c1_fp64_fixed_iterations(R, orc):
     assert rc == 0 and st.iters == ref["iters"] and nrm(phi, ref["phi"]) < 1e-9
 
 
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+@pytest.mark.parametrize("m", [25, 17])
+def test_si_many_slots_ragged(R, orc, prec, m):
+    """One ordinate per task (64 rows x 1 ordinate per lane): a system of 4 m = 100 or 68 partial
+    slots, more than 64 and not a multiple of the combine's 8 waves, so the 8-wave combine takes
+    its ragged tail; fixed iterations against the oracle."""
+    nx, ny = 40, 36
+    f = RI.uniform_fields(nx, ny, 1.0, 0.7, 0.4, 0.6)
+    h = R.Handle(nx, ny, f.sigma_t, f.sigma_s, f.q)
+    p = orc.Problem(nx, ny, f.sigma_t, f.sigma_s, f.q)
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 1, m, seed=3)
+    assert len(w) == 4 * m
+    h.set_ordinates(d, w)
+    phi, st, rc = h.source_iterate(diag_opts(R, prec, 64, 1, tol=-1.0, max_iter=5))
+    ref = orc.source_iterate(p, d, w, None, tol=0.0, max_iter=5)
+    assert st.iters == 5 and st.sweep == R.ROM_SWEEP_DIAG
+    assert nrm(phi, ref["phi"]) < (1e-12 if prec == "fp64" else 1e-5)
+
+
 def test_batch_uneven_and_refresh(R, orc):
     wl = RI.c5(count=6, sides=(16, 40, 100, 300), m_range=(4, 40), master_seed=5)
     hs, probs, sets = [], [], []
