@@ -226,7 +226,7 @@ def main():
         calibrate_copy(a.calibrate_copy)
         return
     if a.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only; --gpus {a.gpus} is not supported", file=sys.stderr)
+        print(f"bench.py runs on one GPU only; --gpus {a.gpus} is not supported", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2407_12527_amd import rom as R

@@ -46,7 +46,7 @@ extern "C" {
 #define ROM_E_NOMEM (-4)    /* host or device allocation failed */
 #define ROM_E_DEVICE (-5)   /* HIP runtime error, or a sweep dependency wait that timed out */
 #define ROM_E_DIVERGED (-6) /* non-finite iterate, or the change grew for 8 iterations in a row */
-#define ROM_E_UNSUPPORTED (-7) /* valid request this build does not implement */
+#define ROM_E_UNSUPPORTED (-7) /* valid request this library does not implement */
 
 /* ---- enums -------------------------------------------------------------------------------- */
 #define ROM_SCHEME_STEP 0 /* first-order upwind cell balance */
