@@ -1426,7 +1426,7 @@ int rom_create(const rom_grid* grid, const double* sigma_t, const double* sigma_
     *out = nullptr;
     if (!grid || !sigma_t || !sigma_s || !q) return fail(nullptr, ROM_E_ARG, "NULL grid or field");
     if (grid->nx <= 0 || grid->ny <= 0) return fail(nullptr, ROM_E_ARG, "nx, ny must be positive");
-    if ((int64_t)grid->nx * grid->ny > (int64_t)1 << 31) return fail(nullptr, ROM_E_ARG, "grid too large");
+    if ((int64_t)grid->nx * grid->ny >= (int64_t)1 << 31) return fail(nullptr, ROM_E_ARG, "grid too large (2^31 cells or more)");
     if (!isfin(grid->x0) || !isfin(grid->x1) || !isfin(grid->y0) || !isfin(grid->y1) || !(grid->x1 > grid->x0) ||
         !(grid->y1 > grid->y0))
         return fail(nullptr, ROM_E_ARG, "grid box must satisfy x1 > x0, y1 > y0");

@@ -81,7 +81,7 @@ def _create(R, st, ss, q, nx=4, ny=3, inflow=None, grid=None):
 
 @pytest.mark.parametrize("case,code", [
     ("sigma_t_zero", -2), ("sigma_s_neg", -2), ("sigma_s_ge_sigma_t", -2), ("q_neg", -2), ("nan", -2),
-    ("nx_zero", -1), ("box", -1), ("inflow_neg", -2)])
+    ("nx_zero", -1), ("box", -1), ("inflow_neg", -2), ("cells_2_31", -1)])
 def test_create_rejects_bad_input(R, case, code):
     cells = 12
     st, ss, q = np.ones(cells), np.full(cells, 0.5), np.ones(cells)
@@ -102,6 +102,9 @@ def test_create_rejects_bad_input(R, case, code):
         grid = R.rom_grid(0, 3, 0.0, 1.0, 0.0, 1.0)
     elif case == "box":
         grid = R.rom_grid(4, 3, 1.0, 0.0, 0.0, 1.0)
+    elif case == "cells_2_31":
+        # refused on the size alone, before the (12-cell) field arrays are read
+        grid = R.rom_grid(65536, 32768, 0.0, 1.0, 0.0, 1.0)
     elif case == "inflow_neg":
         keep = np.array([1.0, -1.0, 0.0])
         inflow = R.rom_inflow(keep.ctypes.data, None, None, None)
