@@ -38,6 +38,32 @@ def test_samples_match_oracle(R, orc, first):
         assert nrm(phis[k], ref) < 1e-9, k
 
 
+@pytest.mark.parametrize("prec,scheme", [("fp32", "step"), ("fp64", "dd"), ("fp32", "dd")])
+def test_samples_with_boundary_inflow(R, orc, prec, scheme):
+    """Isotropic inflow on two faces of a ragged grid with non-square cells: every sample of the
+    ensemble sweeps its own ordinates from the same face values (16-lane groups, four samples per
+    wavefront, one partly filled)."""
+    rng = np.random.default_rng(44)
+    nx, ny = 33, 21
+    st = rng.uniform(0.5, 2.0, nx * ny)
+    ss = st * rng.uniform(0.0, 0.8, nx * ny)
+    q = rng.uniform(0.0, 1.0, nx * ny)
+    inflow = {"left": rng.uniform(0, 1, ny), "top": rng.uniform(0, 1, nx)}
+    box = (0.0, 1.2, 0.0, 0.9)
+    h = R.Handle(nx, ny, st, ss, q, box=box, inflow=inflow)
+    p = orc.Problem(nx, ny, st, ss, q, box=box, inflow=inflow)
+    fp64 = prec == "fp64"
+    sch = R.ROM_SCHEME_DD if scheme == "dd" else R.ROM_SCHEME_STEP
+    o = R.si_opts(tol=-1.0, max_iter=6, precision=R.ROM_PREC_FP64 if fp64 else R.ROM_PREC_FP32, scheme=sch)
+    phis, st_, rc = h.ensemble_samples(5, 21, R.ROM_ORD_STRATIFIED, 2, 2, opts=o)
+    assert rc == R.ROM_NOT_CONVERGED and phis.shape == (5, nx * ny)
+    for k in range(5):
+        d, w = orc.generate(orc.ORD_STRATIFIED, 2, 2, seed=21, sample=k)
+        osch = orc.SCHEME_DD if scheme == "dd" else orc.SCHEME_STEP
+        ref = orc.source_iterate(p, d, w, None, tol=0.0, max_iter=6, scheme=osch)["phi"]
+        assert nrm(phis[k], ref) < (1e-12 if fp64 else 1e-5), k
+
+
 def test_samples_agree_with_moments_and_pieces(R):
     f = RI.checkerboard_fields(40, 40)
     h = R.Handle(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
