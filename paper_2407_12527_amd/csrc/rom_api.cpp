@@ -14,6 +14,7 @@
 #include <functional>
 #include <map>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -365,26 +366,27 @@ bool vec_combine_enabled()
 
 int device_cus()
 {
-    static int cus = 0;
-    if (!cus) {
-        int dev = 0;
-        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
-            cus = 256;
-    }
+    // initialized once per process, thread-safe (function-local static)
+    static const int cus = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        return v;
+    }();
     return cus;
 }
 
 // Frequency of the device real-time clock read by wall_clock64(), in kHz (ticks per ms).
 double wallclock_khz()
 {
-    static double khz = 0.0;
-    if (khz == 0.0) {
+    // initialized once per process, thread-safe (function-local static)
+    static const double khz = [] {
         int dev = 0, v = 0;
         if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
-            khz = v;
-        else
-            khz = 100000.0;
-    }
+            return (double)v;
+        return 100000.0;
+    }();
     return khz;
 }
 
@@ -1699,13 +1701,19 @@ void apply_choice(const TuneChoice& c, rom_si_opts& o)
 // isotropic step-scheme problems, the row-lane kernel's (rows, ordinates per lane).
 void autotune(std::vector<SysInput>& in, rom_si_opts& o, int smode, hipStream_t s)
 {
+    // process-wide choices; the lock covers the lookup and the insertion, not the timing runs (two
+    // threads tuning the same shape at once both measure, the later insertion wins)
     static std::map<std::string, TuneChoice> cache;
+    static std::mutex cache_mu;
     const bool aniso = smode == 2;
     const std::string key = tune_key(in, o, smode);
-    auto it = cache.find(key);
-    if (it != cache.end()) {
-        apply_choice(it->second, o);
-        return;
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        auto it = cache.find(key);
+        if (it != cache.end()) {
+            apply_choice(it->second, o);
+            return;
+        }
     }
     const bool fp64 = o.precision == ROM_PREC_FP64;
     std::vector<TuneChoice> cands;
@@ -1770,7 +1778,10 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, int smode, hipStream_t 
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (pick.sweep == 0) return;  // nothing measurable: keep the heuristic
-    cache[key] = pick;
+    {
+        std::lock_guard<std::mutex> lk(cache_mu);
+        cache[key] = pick;
+    }
     apply_choice(pick, o);
 }
 

@@ -153,3 +153,42 @@ def test_autotuned_shape_reported(R):
     else:
         assert st.sweep == R.ROM_SWEEP_DIAG
         assert st.tile_y in (16, 64) and st.tile_x in (1, 2, 4) and 1 <= st.band <= 16
+
+
+def test_distinct_handles_from_two_threads(R, orc):
+    """Distinct handles are independent: two host threads each build, autotune and solve their
+    own problem at the same time (the library's process-wide tuning cache is shared), and every
+    result matches the oracle."""
+    import threading
+    rng = np.random.default_rng(77)
+    probs = []
+    for k in range(2):
+        nx, ny = 44 + 4 * k, 36
+        st = rng.uniform(0.5, 2.0, nx * ny)
+        ss = st * rng.uniform(0.0, 0.7, nx * ny)
+        q = rng.uniform(0.0, 1.0, nx * ny)
+        d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 2, 3 + k, seed=k)
+        probs.append((nx, ny, st, ss, q, d, w))
+    out = [[None] * 3 for _ in probs]
+    errs = []
+
+    def work(k):
+        try:
+            nx, ny, st, ss, q, d, w = probs[k]
+            h = R.Handle(nx, ny, st, ss, q)
+            h.set_ordinates(d, w)
+            for rep in range(3):
+                out[k][rep] = h.source_iterate(R.si_opts(tol=1e-6))[0]
+        except Exception as e:  # reported after the join
+            errs.append(e)
+
+    ts = [threading.Thread(target=work, args=(k,)) for k in range(2)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join(timeout=120)
+    assert not errs, errs
+    for k, (nx, ny, st, ss, q, d, w) in enumerate(probs):
+        ref = orc.source_iterate(orc.Problem(nx, ny, st, ss, q), d, w, None, tol=1e-6)["phi"]
+        for rep in range(3):
+            assert nrm(out[k][rep], ref) < 1e-5, (k, rep)
