@@ -221,8 +221,9 @@ int rom_ensemble_samples(rom_handle* h, int32_t t, uint64_t seed, int64_t first,
                          const rom_si_opts* opts, double* phis, rom_ens_stats* stats);
 
 /* k independent problems solved together in one persistent sweep launch per iteration; each
- * handle must have ordinates set; phis[i] [cells_i] receives handle i's scalar flux (entries may
- * be NULL); stats (optional) is [k].  All handles must use the same stream and device. */
+ * handle must have ordinates set; phis[i] [cells_i] receives handle i's scalar flux (phis, or any
+ * entry, may be NULL: that flux stays on the device only); stats (optional) is [k].  All handles
+ * must use the same stream and device. */
 int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, double* const* phis,
                     rom_si_stats* stats);
 
