@@ -307,3 +307,22 @@ def test_batch_without_download_then_with(R, orc):
     for a, b, o_, r_ in zip(st0, st1, outs1, refs):
         assert a.iters == b.iters and abs(b.iters - r_["iters"]) <= 1
         assert nrm(o_, r_["phi"]) < 1e-5
+
+
+def test_si_near_critical_many_replays(R, orc):
+    """sigma_s / sigma_t = 0.99 on an optically thick square (20 mean free paths a side): source
+    iteration needs about 420 iterations, so the captured graph is replayed many times (8
+    iterations per replay on the first solve, the previous count split into replays of at most 64
+    on the next).  FP64 iteration count and flux against the oracle; the repeated solve is
+    bitwise identical."""
+    f = RI.uniform_fields(24, 24, 1.0, 0.99, 0.4, 0.6)
+    h, p = both(R, orc, f.nx, f.ny, f.sigma_t, f.sigma_s, f.q, box=(0.0, 20.0, 0.0, 20.0))
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 2, 2, seed=4)
+    h.set_ordinates(d, w)
+    o = R.si_opts(tol=1e-8, max_iter=5000, precision=R.ROM_PREC_FP64)
+    phi, st, rc = h.source_iterate(o)
+    ref = orc.source_iterate(p, d, w, None, tol=1e-8, max_iter=5000)
+    assert rc == 0 and st.iters > 300 and abs(st.iters - ref["iters"]) <= 1
+    assert nrm(phi, ref["phi"]) < (1e-10 if st.iters == ref["iters"] else 1e-7)
+    phi2, st2, rc2 = h.source_iterate(o)
+    assert rc2 == 0 and st2.iters == st.iters and np.array_equal(phi, phi2)
