@@ -100,3 +100,22 @@ def test_samples_argument_errors(R):
         h.ensemble_samples(2, 0, R.ROM_ORD_STRATIFIED, 1, 1, first=-1)
     with pytest.raises(R.RomError):
         h.ensemble_samples(2, 0, R.ROM_ORD_STRATIFIED, 0, 1)
+
+
+@pytest.mark.parametrize("prec", ["fp32", "fp64"])
+def test_ensemble_moments_across_batches(R, prec):
+    """More samples than one launch takes (1024): the ensemble runs as 1024 + 76 samples and the
+    batches' FP64 moments are merged by the pairwise update; mean and variance against two-pass
+    moments of all 1100 per-sample fluxes (the same fluxes, taken by the per-sample call)."""
+    f = RI.uniform_fields(12, 10, 1.0, 0.5, 0.3, 0.7)
+    h = R.Handle(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    o = R.si_opts(tol=1e-10 if prec == "fp64" else 1e-6,
+                  precision=R.ROM_PREC_FP64 if prec == "fp64" else R.ROM_PREC_FP32)
+    t = 1100
+    phis, st1, rc1 = h.ensemble_samples(t, 5, R.ROM_ORD_STRATIFIED, 2, 2, opts=o)
+    mean, var, st2, rc2 = h.ensemble(t, 5, R.ROM_ORD_STRATIFIED, 2, 2, o)
+    assert rc1 == 0 and rc2 == 0 and st1.samples == t and st2.samples == t
+    m = phis.mean(axis=0)
+    v = ((phis - m) ** 2).sum(axis=0) / (t - 1)
+    np.testing.assert_allclose(mean, m, rtol=1e-13, atol=0)
+    np.testing.assert_allclose(var, v, rtol=1e-9, atol=1e-300)
