@@ -21,8 +21,13 @@
  *   - input arrays are copied during the call; the caller keeps ownership;
  *   - cell arrays are [ny][nx] doubles, x fastest: cell (i, j) at j*nx + i;
  *   - ordinate arrays keep the caller's ordinate order; dirs is [n][3] = (c, s, zeta);
- *   - a handle owns its device memory and queues all work on its stream (default: the null
- *     stream); a handle is not thread-safe, distinct handles are independent;
+ *   - a handle owns its device memory and queues all work on its stream (default: a
+ *     non-blocking stream of its own; rom_set_stream binds the caller's);
+ *   - a handle is not thread-safe; distinct handles may be used from different threads, and
+ *     the calls that touch the device then run one at a time (a process-wide lock: the first
+ *     solve of a shape captures a HIP graph, which HIP fails if another thread meanwhile issues
+ *     work that synchronizes with it; work the caller issues outside librom from other threads
+ *     during such a solve can do the same and make it return ROM_E_DEVICE);
  *   - on error the handle keeps a message readable with rom_last_error().
  */
 #ifndef ROM_H

@@ -29,6 +29,17 @@ namespace {
 // ------------------------------------------------------------------------------------ utilities
 thread_local std::string g_create_error;
 
+// Entry points that touch the device hold this process-wide lock for their whole duration: a
+// first solve of a batch shape captures a HIP graph, and HIP fails a capture when another thread
+// meanwhile issues work that would synchronize with it (a synchronous copy, a free).  Calls from
+// different threads therefore run one at a time; recursive because entry points may nest.
+std::recursive_mutex& api_mutex()
+{
+    static std::recursive_mutex m;
+    return m;
+}
+#define ROM_API_LOCK std::lock_guard<std::recursive_mutex> rom_api_lock_(api_mutex())
+
 struct DevMem {
     void* p = nullptr;
     size_t bytes = 0;
@@ -1424,6 +1435,7 @@ int rom_generate_ordinates(const rom_ord_spec* spec, uint64_t seed, int64_t samp
 int rom_create(const rom_grid* grid, const double* sigma_t, const double* sigma_s, const double* q,
                const rom_inflow* inflow, rom_handle** out)
 {
+    ROM_API_LOCK;
     if (!out) return fail(nullptr, ROM_E_ARG, "out is NULL");
     *out = nullptr;
     if (!grid || !sigma_t || !sigma_s || !q) return fail(nullptr, ROM_E_ARG, "NULL grid or field");
@@ -1471,7 +1483,11 @@ int rom_create(const rom_grid* grid, const double* sigma_t, const double* sigma_
     return ROM_OK;
 }
 
-void rom_destroy(rom_handle* h) { delete h; }
+void rom_destroy(rom_handle* h)
+{
+    ROM_API_LOCK;
+    delete h;
+}
 
 int rom_set_stream(rom_handle* h, void* stream)
 {
@@ -1554,6 +1570,7 @@ int rom_phi_device(const rom_handle* h, const void** dev, int32_t* is_fp64)
 int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double* phi, double* psi,
               const rom_si_opts* opts)
 {
+    ROM_API_LOCK;
     if (!h) return ROM_E_ARG;
     if (!src || !phi) return fail(h, ROM_E_ARG, "src and phi must be non-NULL");
     if (h->n == 0) return fail(h, ROM_E_STATE, "set ordinates first");
@@ -1911,6 +1928,7 @@ extern "C" {
 
 int rom_source_iterate(rom_handle* h, const rom_si_opts* opts, double* phi, rom_si_stats* stats)
 {
+    ROM_API_LOCK;
     if (!h) return ROM_E_ARG;
     if (h->n == 0) return fail(h, ROM_E_STATE, "set ordinates first");
     rom_si_opts o;
@@ -1958,6 +1976,7 @@ int rom_source_iterate(rom_handle* h, const rom_si_opts* opts, double* phi, rom_
 
 int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, double* const* phis, rom_si_stats* stats)
 {
+    ROM_API_LOCK;
     if (!hs || k <= 0) return fail(nullptr, ROM_E_ARG, "need at least one handle");
     rom_handle* h0 = hs[0];
     if (!h0) return fail(nullptr, ROM_E_ARG, "NULL handle");
@@ -2024,6 +2043,7 @@ int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, d
 int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* spec, const rom_si_opts* opts, double* mean,
                  double* var, rom_ens_stats* stats)
 {
+    ROM_API_LOCK;
     if (!h) return ROM_E_ARG;
     if (t <= 0 || !spec) return fail(h, ROM_E_ARG, "t must be > 0 and spec non-NULL");
     rom_si_opts o;
@@ -2073,6 +2093,7 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
 int rom_ensemble_samples(rom_handle* h, int32_t t, uint64_t seed, int64_t first, const rom_ord_spec* spec,
                          const rom_si_opts* opts, double* phis, rom_ens_stats* stats)
 {
+    ROM_API_LOCK;
     if (!h) return ROM_E_ARG;
     if (t <= 0 || !spec || !phis || first < 0) return fail(h, ROM_E_ARG, "t > 0, first >= 0, spec and phis non-NULL");
     rom_si_opts o;
@@ -2206,6 +2227,7 @@ extern "C" {
 int rom_slab_create(int32_t nx, double x0, double x1, const double* sigma_t, const double* sigma_s, const double* q,
                     rom_slab** out)
 {
+    ROM_API_LOCK;
     if (!out) return slab_fail(nullptr, ROM_E_ARG, "out is NULL");
     *out = nullptr;
     if (!sigma_t || !sigma_s || !q) return slab_fail(nullptr, ROM_E_ARG, "NULL field");
@@ -2233,7 +2255,11 @@ int rom_slab_create(int32_t nx, double x0, double x1, const double* sigma_t, con
     }
 }
 
-void rom_slab_destroy(rom_slab* sl) { delete sl; }
+void rom_slab_destroy(rom_slab* sl)
+{
+    ROM_API_LOCK;
+    delete sl;
+}
 
 int rom_slab_set_stream(rom_slab* sl, void* stream)
 {
@@ -2245,6 +2271,7 @@ int rom_slab_set_stream(rom_slab* sl, void* stream)
 int rom_slab_solve(rom_slab* sl, int32_t t, int32_t n, const double* mu, const double* w, const double* inflow,
                    const rom_si_opts* opts, double* phis, int32_t* iters, rom_ens_stats* stats)
 {
+    ROM_API_LOCK;
     if (!sl) return ROM_E_ARG;
     if (t < 1 || n < 1 || n > 4096) return slab_fail(sl, ROM_E_ARG, "need t >= 1 and 1 <= n <= 4096");
     if (!mu || !w || !inflow || !phis) return slab_fail(sl, ROM_E_ARG, "NULL mu, w, inflow or phis");

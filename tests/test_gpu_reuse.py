@@ -155,40 +155,75 @@ def test_autotuned_shape_reported(R):
         assert st.tile_y in (16, 64) and st.tile_x in (1, 2, 4) and 1 <= st.band <= 16
 
 
-def test_distinct_handles_from_two_threads(R, orc):
-    """Distinct handles are independent: two host threads each build, autotune and solve their
-    own problem at the same time (the library's process-wide tuning cache is shared), and every
-    result matches the oracle."""
+def test_distinct_handles_from_several_threads(R, orc):
+    """Distinct handles may be used from different threads: four host threads each build, autotune
+    and solve three problems of their own shapes at the same time (every first solve of a shape
+    captures a graph while the other threads allocate, copy and free), and every result matches
+    the oracle."""
     import threading
     rng = np.random.default_rng(77)
+    nthreads, per = 4, 3
     probs = []
-    for k in range(2):
-        nx, ny = 44 + 4 * k, 36
+    for k in range(nthreads * per):
+        nx, ny = 20 + 4 * (k % 5), 16 + 2 * (k % 3)
         st = rng.uniform(0.5, 2.0, nx * ny)
         ss = st * rng.uniform(0.0, 0.7, nx * ny)
         q = rng.uniform(0.0, 1.0, nx * ny)
-        d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 2, 3 + k, seed=k)
+        d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 1 + k % 2, 2 + k % 3, seed=k)
         probs.append((nx, ny, st, ss, q, d, w))
-    out = [[None] * 3 for _ in probs]
+    out = [None] * len(probs)
     errs = []
 
-    def work(k):
+    def work(i):
         try:
-            nx, ny, st, ss, q, d, w = probs[k]
-            h = R.Handle(nx, ny, st, ss, q)
-            h.set_ordinates(d, w)
-            for rep in range(3):
-                out[k][rep] = h.source_iterate(R.si_opts(tol=1e-6))[0]
+            for k in range(i * per, (i + 1) * per):
+                nx, ny, st, ss, q, d, w = probs[k]
+                h = R.Handle(nx, ny, st, ss, q)
+                h.set_ordinates(d, w)
+                out[k] = h.source_iterate(R.si_opts(tol=1e-6))[0]
+                h.close()
         except Exception as e:  # reported after the join
             errs.append(e)
 
-    ts = [threading.Thread(target=work, args=(k,)) for k in range(2)]
-    for t in ts:
-        t.start()
-    for t in ts:
-        t.join(timeout=120)
-    assert not errs, errs
-    for k, (nx, ny, st, ss, q, d, w) in enumerate(probs):
-        ref = orc.source_iterate(orc.Problem(nx, ny, st, ss, q), d, w, None, tol=1e-6)["phi"]
-        for rep in range(3):
-            assert nrm(out[k][rep], ref) < 1e-5, (k, rep)
+    refs = [orc.source_iterate(orc.Problem(nx, ny, st, ss, q), d, w, None, tol=1e-6)["phi"]
+            for (nx, ny, st, ss, q, d, w) in probs]
+    for rnd in range(3):  # the threads' calls interleave differently each round
+        out[:] = [None] * len(probs)
+        ts = [threading.Thread(target=work, args=(i,)) for i in range(nthreads)]
+        for t in ts:
+            t.start()
+        for t in ts:
+            t.join(timeout=120)
+        assert not errs, (rnd, errs)
+        for k in range(len(probs)):
+            assert nrm(out[k], refs[k]) < 1e-5, (rnd, k)
+
+
+def test_solve_on_a_caller_stream(R, orc):
+    """A handle bound to a caller's HIP stream (a torch stream at default priority) runs its plan
+    there: the result is bitwise that of the default-stream solve of a twin handle, the device
+    result is readable after the stream's work, and the ensemble path works on it too."""
+    import torch
+    rng = np.random.default_rng(8)
+    nx, ny = 40, 28
+    st, ss, q = rand_problem(rng, nx, ny, 0.8)
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 2, 4, seed=6)
+    a = R.Handle(nx, ny, st, ss, q)
+    a.set_ordinates(d, w)
+    phi_a, _, rc = a.source_iterate(R.si_opts(tol=1e-6))
+    assert rc == 0
+    b = R.Handle(nx, ny, st, ss, q)
+    s = torch.cuda.Stream()
+    b.use_torch_stream(s)
+    b.set_ordinates(d, w)
+    with torch.cuda.stream(s):
+        phi_b, _, rc = b.source_iterate(R.si_opts(tol=1e-6))
+        dev = b.phi_device_tensor()
+    s.synchronize()
+    assert rc == 0 and np.array_equal(phi_a, phi_b)
+    np.testing.assert_array_equal(dev.cpu().numpy().astype(np.float64), phi_b)
+    mean_a, _, _, rc_a = a.ensemble(6, 2, R.ROM_ORD_STRATIFIED, 2, 2, R.si_opts(tol=1e-6))
+    mean_b, _, _, rc_b = b.ensemble(6, 2, R.ROM_ORD_STRATIFIED, 2, 2, R.si_opts(tol=1e-6))
+    assert rc_a == 0 and rc_b == 0 and np.array_equal(mean_a, mean_b)
+    ref = orc.source_iterate(orc.Problem(nx, ny, st, ss, q), d, w, None, tol=1e-6)["phi"]
+    assert nrm(phi_b, ref) < 1e-5
