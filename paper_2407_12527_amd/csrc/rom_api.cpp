@@ -1368,7 +1368,7 @@ int validate_opts(rom_handle* h, const rom_si_opts* o, rom_si_opts& out)
     if (out.sweep == ROM_SWEEP_DIAG && out.scheme != ROM_SCHEME_STEP)
         return fail(h, ROM_E_UNSUPPORTED, "the row-lane sweep implements the step scheme only");
     if ((out.tile_x != 0 || out.tile_y != 0) && !sweep_tile_supported(out.tile_x, out.tile_y))
-        return fail(h, ROM_E_ARG, "unsupported tile shape (8x4, 8x8, 16x8, 16x16, 32x16)");
+        return fail(h, ROM_E_ARG, "unsupported tile shape (8x4, 8x8, 16x8, 16x16)");
     return ROM_OK;
 }
 
