@@ -94,3 +94,71 @@ def test_random_configuration(R, orc, seed):
                              tol=0.0, max_iter=4)["phi"]
     summary = {k: c[k] for k in ("nx", "ny", "fp64", "dd", "scat", "norm", "kw")}
     assert nrm(phi, ref) < c["tol"], (summary, len(c["w"]))
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_ensemble(R, orc, seed):
+    """Ensembles: random grid, stratified spec, sample count (several samples share a wavefront
+    when a quadrant holds 16 or 32 ordinates), scheme, precision and scattering kind; each
+    sample's flux after four iterations against the oracle on the same bit-identical set."""
+    rng = np.random.default_rng(7000 + seed)
+    nx, ny = int(rng.integers(3, 41)), int(rng.integers(3, 41))
+    cells = nx * ny
+    st = rng.uniform(0.3, 2.5, cells)
+    ss = st * rng.uniform(0.0, 0.85, cells)
+    q = rng.uniform(0.0, 1.0, cells)
+    inflow = {"bottom": rng.uniform(0, 1, nx)} if rng.uniform() < 0.5 else None
+    nz, nt = int(rng.integers(1, 4)), int(rng.integers(1, 5))
+    t = int(rng.integers(1, 13))
+    seed_o = int(rng.integers(0, 1 << 30))
+    fp64 = bool(rng.uniform() < 0.5)
+    dd = bool(rng.uniform() < 0.3)
+    scat = ["iso", "linear", "hg"][int(rng.integers(0, 3))]
+    h = R.Handle(nx, ny, st, ss, q, inflow=inflow)
+    p = orc.Problem(nx, ny, st, ss, q, inflow=inflow)
+    ok = None
+    if scat != "iso":
+        rk, ok = (R.ROM_SCAT_LINEAR, orc.SCAT_LINEAR) if scat == "linear" else (R.ROM_SCAT_HG, orc.SCAT_HG)
+        h.set_scattering(rk | R.ROM_SCAT_NORMALIZE, 0.7)
+    o = R.si_opts(tol=-1.0, max_iter=4, precision=R.ROM_PREC_FP64 if fp64 else R.ROM_PREC_FP32,
+                  scheme=R.ROM_SCHEME_DD if dd else R.ROM_SCHEME_STEP)
+    phis, st_, rc = h.ensemble_samples(t, seed_o, R.ROM_ORD_STRATIFIED, nz, nt, opts=o)
+    assert rc == R.ROM_NOT_CONVERGED and phis.shape == (t, cells)
+    tol = 1e-11 if fp64 else (2e-3 if scat == "hg" else 1e-5)
+    for k in range(t):
+        d, w = orc.generate(orc.ORD_STRATIFIED, nz, nt, seed=seed_o, sample=k)
+        W = None if ok is None else orc.build_W(d, w, ok | orc.SCAT_NORMALIZE, 0.7, fold=1)
+        ref = orc.source_iterate(p, d, w, W, scheme=orc.SCHEME_DD if dd else orc.SCHEME_STEP, tol=0.0,
+                                 max_iter=4)["phi"]
+        assert nrm(phis[k], ref) < tol, (k, nx, ny, nz, nt, t, fp64, dd, scat)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_batch(R, orc, seed):
+    """Batches of 2 to 6 uneven problems in one persistent launch per iteration (random sizes,
+    ordinate sets and counts, isotropic scattering); four iterations of each against the oracle."""
+    rng = np.random.default_rng(8000 + seed)
+    k = int(rng.integers(2, 7))
+    fp64 = bool(rng.uniform() < 0.5)
+    hs, refs = [], []
+    for i in range(k):
+        nx, ny = int(rng.integers(2, 49)), int(rng.integers(2, 49))
+        cells = nx * ny
+        st = rng.uniform(0.3, 2.5, cells)
+        ss = st * rng.uniform(0.0, 0.85, cells)
+        q = rng.uniform(0.0, 1.0, cells)
+        if rng.uniform() < 0.5:
+            d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, int(rng.integers(1, 4)), int(rng.integers(1, 6)),
+                                        seed=int(rng.integers(0, 1 << 30)))
+        else:
+            d, w = R.generate_ordinates(R.ROM_ORD_IID_SPHERE, int(rng.integers(4, 33)), seed=int(rng.integers(0, 1 << 30)))
+        h = R.Handle(nx, ny, st, ss, q)
+        h.set_ordinates(d, w)
+        hs.append(h)
+        refs.append(orc.source_iterate(orc.Problem(nx, ny, st, ss, q), d, w, None, tol=0.0, max_iter=4)["phi"])
+    o = R.si_opts(tol=-1.0, max_iter=4, precision=R.ROM_PREC_FP64 if fp64 else R.ROM_PREC_FP32)
+    outs, stats, rc = R.solve_batch(hs, o)
+    assert rc == R.ROM_NOT_CONVERGED
+    for i in range(k):
+        assert stats[i].iters == 4
+        assert nrm(outs[i], refs[i]) < (1e-11 if fp64 else 1e-5), (i, k, fp64)
