@@ -162,3 +162,35 @@ def test_random_batch(R, orc, seed):
     for i in range(k):
         assert stats[i].iters == 4
         assert nrm(outs[i], refs[i]) < (1e-11 if fp64 else 1e-5), (i, k, fp64)
+
+
+@pytest.mark.parametrize("seed", range(16))
+def test_random_slab(R, orc, seed):
+    """Slab geometry: random grid (1 to 200 cells), fields, interval, ROM sets or Gauss / midpoint
+    quadratures of random even size, a ragged number of systems per launch, random inflow values;
+    five iterations in FP64 (max-norm 1e-12) or FP32 (normwise 1e-5) against the oracle."""
+    rng = np.random.default_rng(6000 + seed)
+    nx = int(rng.integers(1, 201))
+    x0 = float(rng.uniform(-1.0, 1.0))
+    x1 = x0 + float(rng.uniform(0.2, 4.0))
+    st = rng.uniform(0.3, 3.0, nx + 1)
+    ss = st * rng.uniform(0.0, 0.9, nx + 1)
+    q = rng.uniform(0.0, 1.0, nx + 1)
+    s = R.Slab(nx, st, ss, q, x0=x0, x1=x1)
+    n = 2 * int(rng.integers(1, 21))
+    kind = int(rng.integers(0, 3))
+    t = int(rng.integers(1, 71)) if kind == R.ROM_SLAB_RANDOM else 1
+    sets = [R.slab_ordinates(kind, n, 17, k) for k in range(t)]
+    mu = np.array([m for m, _ in sets])
+    w = np.array([x for _, x in sets])
+    inflow = rng.uniform(0.0, 2.0, (t, n))
+    fp64 = bool(rng.uniform() < 0.5)
+    phis, iters, st_, rc = s.solve(mu, w, inflow, R.si_opts(tol=-1.0, max_iter=5,
+                                                          precision=R.ROM_PREC_FP64 if fp64 else R.ROM_PREC_FP32))
+    assert rc == R.ROM_NOT_CONVERGED and np.all(iters == 5)
+    for k in range(t):
+        ref = orc.slab_source_iterate(nx, x0, x1, st, ss, q, mu[k], w[k], inflow[k], tol=0.0, max_iter=5)["phi"]
+        if fp64:
+            assert np.max(np.abs(phis[k] - ref)) <= 1e-12 * np.max(np.abs(ref)), (k, nx, n, kind, t)
+        else:
+            assert nrm(phis[k], ref) < 1e-5, (k, nx, n, kind, t)
