@@ -227,3 +227,28 @@ def test_slab_create_and_solve_validation(R):
     o.precision = 7
     with pytest.raises(R.RomError):
         s.solve(mu, w, np.ones(4), o)
+
+
+def test_empty_counts_are_refused(R):
+    """Zero or negative sample, system and ordinate counts are argument errors, found on the host
+    before any device work."""
+    import ctypes as Cc
+    h = R.Handle(8, 8, np.ones(64), np.full(64, 0.5), np.ones(64))
+    for t in (0, -1):
+        with pytest.raises(R.RomError) as e:
+            h.ensemble(t, 1, R.ROM_ORD_STRATIFIED, 1, 1)
+        assert e.value.status == R.ROM_E_ARG
+    with pytest.raises(R.RomError) as e:
+        h.ensemble_samples(0, 1, R.ROM_ORD_STRATIFIED, 1, 1)
+    assert e.value.status == R.ROM_E_ARG
+    x = np.linspace(0, 1, 9)
+    s = R.Slab(8, 1 + x, 0.5 * (1 + x), np.ones(9))
+    mu, w = R.slab_ordinates(R.ROM_SLAB_RANDOM, 4, 1, 0)
+    inflow = np.ones(4)
+    phis = np.empty((1, 9))
+    it = np.zeros(1, dtype=np.int32)
+    st = R.rom_ens_stats()
+    for t, n in ((0, 4), (1, 0), (-1, 4), (1, -2)):
+        rc = R.lib().rom_slab_solve(s.s, t, n, mu.ctypes.data, w.ctypes.data, inflow.ctypes.data, None,
+                                    phis.ctypes.data, it.ctypes.data, Cc.byref(st))
+        assert rc == R.ROM_E_ARG, (t, n)
