@@ -1713,8 +1713,8 @@ void apply_choice(const TuneChoice& c, rom_si_opts& o)
     }
 }
 
-// Time three sweep + combine steps of every candidate on the real buffers of this batch shape
-// (zero sources) and keep the fastest for the process.  Candidates: the strip kernel's tiles x bands, and, for
+// Time sweep + combine steps of every candidate on the real buffers of this batch shape (zero
+// sources) and keep the fastest for the process.  Candidates: the strip kernel's tiles x bands, and, for
 // isotropic step-scheme problems, the row-lane kernel's (rows, ordinates per lane).
 void autotune(std::vector<SysInput>& in, rom_si_opts& o, int smode, hipStream_t s)
 {
@@ -1749,9 +1749,11 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, int smode, hipStream_t 
     }
     float best = 1e30f;
     TuneChoice pick;
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    // each candidate: one warm-up step, then kSteps steps timed one by one; its score is the
+    // fastest step (robust to launch jitter, which a single short measurement is not)
+    constexpr int kSteps = 5;
+    hipEvent_t ev[kSteps + 1];
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
     for (const TuneChoice& cand : cands) {
         rom_si_opts c = o;
         apply_choice(cand, c);
@@ -1766,20 +1768,23 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, int smode, hipStream_t 
             continue;
         HIPCHK(launch_fill(P.src_ptr(), P.src_len, P.fp64, 0.0, s));
         if (aniso) HIPCHK(launch_fill(P.d_ang.p, (int64_t)(P.d_ang.bytes / P.esz), P.fp64, 0.0, s));
-        float ms = 0.f;
         const CombineArgs ca = P.combine_args(1, 0.0);
-        for (int rep = 0; rep < 3; ++rep) {
+        for (int rep = 0; rep <= kSteps; ++rep) {
             HIPCHK(launch_reset_systems(P.d_sysctl.as<SysCtl>(), P.nsys, P.d_ctl.as<Ctl>(), s));
-            if (rep == 1) HIPCHK(hipEventRecord(e0, s));
+            if (rep >= 1) HIPCHK(hipEventRecord(ev[rep - 1], s));
             HIPCHK(P.launch_sweep_any(1, s));
             HIPCHK(launch_combine(ca, (int)P.cblocks.size(), P.fp64, s));  // a source-iteration step is both
         }
-        HIPCHK(hipEventRecord(e1, s));
-        HIPCHK(hipEventSynchronize(e1));
-        HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+        HIPCHK(hipEventRecord(ev[kSteps], s));
+        HIPCHK(hipEventSynchronize(ev[kSteps]));
+        float score = 1e30f;
+        for (int k = 0; k < kSteps; ++k) {
+            float ms = 0.f;
+            HIPCHK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            score = std::min(score, ms);
+        }
         Ctl ctl{};
         HIPCHK(hipMemcpy(&ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost));
-        const float score = ms;
         if (!ctl.error && score < best) {
             best = score;
             pick = cand;
@@ -1792,8 +1797,7 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, int smode, hipStream_t 
             }
         }
     }
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    for (auto& e : ev) (void)hipEventDestroy(e);
     if (pick.sweep == 0) return;  // nothing measurable: keep the heuristic
     {
         std::lock_guard<std::mutex> lk(cache_mu);
