@@ -43,7 +43,8 @@ KERNEL_SOURCES = {
 }
 MEASURED_TRAFFIC = {  # workload: [(kernel family, shape as in config, source hash, bytes per launch), ...]
     "c2": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 1, "waves_per_group": 4}, "e1f013e8ca59fc4f", 25516675),
-           ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "e1f013e8ca59fc4f", 38900795)],
+           ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "e1f013e8ca59fc4f", 38900795),
+           ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 2}, "e1f013e8ca59fc4f", 40638020)],
     "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "e1f013e8ca59fc4f", 1810208),
            ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 1}, "e1f013e8ca59fc4f", 1825374)],
     "c3": [("strip", {"sweep_tile": "16x16", "band": 4}, "77c60af2502977e7", 938147087)],
