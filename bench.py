@@ -47,9 +47,9 @@ MEASURED_TRAFFIC = {  # workload: [(kernel family, shape as in config, source ha
            ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 2}, "e1f013e8ca59fc4f", 40638020)],
     "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "e1f013e8ca59fc4f", 1810208),
            ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 1}, "e1f013e8ca59fc4f", 1825374)],
-    "c3": [("strip", {"sweep_tile": "16x16", "band": 4}, "77c60af2502977e7", 938147087)],
-    "c4": [("strip", {"sweep_tile": "8x4", "band": 4}, "77c60af2502977e7", 446438498)],
-    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "77c60af2502977e7", 2725930859)],
+    "c3": [("strip", {"sweep_tile": "16x16", "band": 4}, "18d77716fe5ec93c", 938536546)],
+    "c4": [("strip", {"sweep_tile": "8x4", "band": 4}, "18d77716fe5ec93c", 446640762)],
+    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "18d77716fe5ec93c", 2737417550)],
 }
 
 

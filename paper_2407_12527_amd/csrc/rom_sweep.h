@@ -452,7 +452,17 @@ __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
                     for (int r = 0; r < TY; ++r)
                         if (r < rows) do_row(r);
                 } else {
-                    for (int r = 0; r < rows; ++r) do_row(r);
+                    int r = 0;
+                    if constexpr (MOM == 1 && PSI == 0) {
+                        // isotropic flux-only sweeps take rows in pairs: the second row takes the
+                        // first's y-face values directly, halving the register moves that carry
+                        // them around the loop (the other variants would lose a wave of occupancy)
+                        for (; r + 1 < rows; r += 2) {
+                            do_row(r);
+                            do_row(r + 1);
+                        }
+                    }
+                    for (; r < rows; ++r) do_row(r);
                 }
                 if (to_global) {
 #pragma unroll
