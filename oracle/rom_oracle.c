@@ -14,7 +14,7 @@
  * orders, one ordinate sweep at a time (ordinates may run on separate OpenMP threads, since
  * they are independent once the source is fixed), and sums taken in index order.
  *
- * Readings of points the paper leaves open (each is also listed in the design notes):
+ * Readings of points the paper leaves open:
  *   - spatial scheme: first-order upwind ("step") on the main path; the paper's own diamond
  *     difference (Sec. 2) is available as ORC_SCHEME_DD;
  *   - source iteration starts from phi^0 = 0 (the Neumann series of Sec. 3.2, eq. (3.10)) and

@@ -6,8 +6,8 @@ paper uses 10 240) the expected per-sample error E = mean ||phi^xi - phi_ref||_2
 about 1 %, so it is compared with the printed values to 5 %, and its order in Delta S = pi/(4N^2)
 to 0.03 of the printed 0.74.  The bias at N >= 3 is of the size of the Monte Carlo noise (the
 paper's as well), so the bias is only required to fall with order above 1 and to be within a
-factor 1.6 of the printed values at N = 1, 2 (the paper's sampler is described in words only;
-readings in the design notes)."""
+factor 1.6 of the printed values at N = 1, 2 (the paper describes its sampler in words only, so
+the stratified sampler here is one reading of that description)."""
 import math
 import os
 

@@ -651,8 +651,9 @@ def test_paper_table1_uniform_linear_kernel_fold(orc):
 
 def test_paper_table1_gauss_close(orc):
     """Table 1, 2D Gaussian quadrature, g = 0: with the Appendix A construction as read here the
-    errors agree with the printed ones to within 4 % (not to every digit; see the design notes),
-    and the convergence order is the printed 0.82 to within 0.06."""
+    errors agree with the printed ones to within 4 % but not to every digit (the text leaves some
+    detail of the authors' construction open), and the convergence order is the printed 0.82 to
+    within 0.06."""
     f = RI.example21()
     prob = _prob(orc, f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
     ref_d, ref_w = orc.generate(orc.ORD_GAUSS2D, 20)
