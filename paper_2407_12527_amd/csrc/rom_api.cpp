@@ -234,8 +234,14 @@ struct Plan {
     DevMem d_citems, d_cmap;  // batched contraction: per-system arguments, (system, block) map
     int cmap_blocks = 0;
     std::vector<int64_t> pt_off;  // per system offset into d_Pt (elements)
-    hipGraphExec_t gexec = nullptr;
+    hipGraphExec_t gexec = nullptr;   // K iterations
     hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec0 = nullptr;  // the initial state followed by K iterations (first replay)
+    hipGraph_t graph0 = nullptr;
+    // pinned host copy of the control block and the per-system states, read back after every
+    // replay (a pageable destination would be staged through a bounce buffer, copy by copy)
+    void* h_state = nullptr;
+    size_t h_state_bytes = 0;
     int graph_iters = 0;
     int last_iters = 0;   // largest iteration count of the previous solve with this plan
     double graph_tol = 0.0;
@@ -245,6 +251,9 @@ struct Plan {
     {
         if (gexec) (void)hipGraphExecDestroy(gexec);
         if (graph) (void)hipGraphDestroy(graph);
+        if (gexec0) (void)hipGraphExecDestroy(gexec0);
+        if (graph0) (void)hipGraphDestroy(graph0);
+        if (h_state) (void)hipHostFree(h_state);
     }
 
     // the sigma_t and source pools carry kPoolPad elements of padding on both sides
@@ -1250,63 +1259,86 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     HIPCHK(hipEventRecord(e0, s));
-    // initial state: phi = 0, isotropic source = q (linear kernel: S0 = q, S1 = S2 = 0), angular flux = 0
-    int64_t phi_total = 0;
-    for (auto& sd : P.sys) phi_total = std::max<int64_t>(phi_total, sd.phi_off + P.handles[sd.prob]->cells);
-    HIPCHK(launch_fill(P.d_phi.p, phi_total, P.fp64, 0.0, s));
-    if (P.nmom == 4) HIPCHK(launch_fill(P.src_ptr(), P.src_len, P.fp64, 0.0, s));  // S1 = S2 = 0
-    int64_t max_cells = 0;
-    for (auto& sd : P.sys) max_cells = std::max<int64_t>(max_cells, P.handles[sd.prob]->cells);
-    HIPCHK(launch_init_source(P.d_sys.as<SystemDev>(), P.d_probs.as<ProblemDev>(), P.nsys, max_cells, P.fp64, P.d_q.p,
-                              P.src_ptr(), s));
-    if (P.aniso) {
-        int64_t tot = 0;
-        for (int k = 0; k < P.nsys; ++k) tot = std::max<int64_t>(tot, P.sys[k].ang_off + P.handles[P.sys[k].prob]->cells * (int64_t)P.npad_al[k]);
-        if (P.fp64) HIPCHK(launch_fill(P.d_psi.p, tot, true, 0.0, s));
-        else HIPCHK(launch_fill(P.d_psi.p, (tot + 1) / 2, false, 0.0, s));  // BF16 zeros are float zeros
+    // initial state: phi = 0, isotropic source = q (linear kernel: S0 = q, S1 = S2 = 0), angular
+    // flux = 0, every system active.  Its arguments are fixed for a plan, so it is captured at the
+    // head of the first replay's graph: a solve that stops within K iterations is one launch.
+    int64_t phi_total = 0, max_cells = 0, psi_total = 0;
+    for (auto& sd : P.sys) {
+        phi_total = std::max<int64_t>(phi_total, sd.phi_off + P.handles[sd.prob]->cells);
+        max_cells = std::max<int64_t>(max_cells, P.handles[sd.prob]->cells);
     }
-    HIPCHK(launch_reset_systems(P.d_sysctl.as<SysCtl>(), P.nsys, P.d_ctl.as<Ctl>(), s));
-
-    if (!P.gexec || P.graph_iters != K || P.graph_stream != s || P.graph_tol != tol) {
-        if (P.gexec) {
-            (void)hipGraphExecDestroy(P.gexec);
-            P.gexec = nullptr;
+    if (P.aniso)
+        for (int k = 0; k < P.nsys; ++k)
+            psi_total = std::max<int64_t>(psi_total, P.sys[k].ang_off + P.handles[P.sys[k].prob]->cells * (int64_t)P.npad_al[k]);
+    auto enqueue_initial_state = [&]() {
+        if (P.nmom == 4) HIPCHK(launch_fill(P.src_ptr(), P.src_len, P.fp64, 0.0, s));  // S1 = S2 = 0
+        if (P.aniso) {
+            if (P.fp64) HIPCHK(launch_fill(P.d_psi.p, psi_total, true, 0.0, s));
+            else HIPCHK(launch_fill(P.d_psi.p, (psi_total + 1) / 2, false, 0.0, s));  // BF16 zeros are float zeros
         }
-        if (P.graph) {
-            (void)hipGraphDestroy(P.graph);
-            P.graph = nullptr;
-        }
+        HIPCHK(launch_init_state(P.d_sys.as<SystemDev>(), P.d_probs.as<ProblemDev>(), P.nsys, max_cells, P.fp64, P.d_q.p,
+                                 P.src_ptr(), P.d_phi.p, phi_total, P.d_sysctl.as<SysCtl>(), P.d_ctl.as<Ctl>(), s));
+    };
+    auto capture = [&](bool with_initial_state, hipGraph_t& g, hipGraphExec_t& ge) {
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
-            HIPCHK(launch_mark(P.d_ctl.as<Ctl>(), s));
+            if (with_initial_state) enqueue_initial_state();
+            HIPCHK(launch_mark(P.d_ctl.as<Ctl>(), s));  // the sweep is timed from here, not from the combine
             for (int k = 0; k < K; ++k) enqueue_iteration(P, s, tol);
         } catch (...) {
-            hipGraph_t g;
-            (void)hipStreamEndCapture(s, &g);
-            if (g) (void)hipGraphDestroy(g);
+            hipGraph_t gg = nullptr;
+            (void)hipStreamEndCapture(s, &gg);
+            if (gg) (void)hipGraphDestroy(gg);
             throw;
         }
-        HIPCHK(hipStreamEndCapture(s, &P.graph));
-        HIPCHK(hipGraphInstantiate(&P.gexec, P.graph, nullptr, nullptr, 0));
+        HIPCHK(hipStreamEndCapture(s, &g));
+        HIPCHK(hipGraphInstantiate(&ge, g, nullptr, nullptr, 0));
+    };
+
+    if (!P.gexec || !P.gexec0 || P.graph_iters != K || P.graph_stream != s || P.graph_tol != tol) {
+        for (hipGraphExec_t* ge : {&P.gexec, &P.gexec0})
+            if (*ge) {
+                (void)hipGraphExecDestroy(*ge);
+                *ge = nullptr;
+            }
+        for (hipGraph_t* g : {&P.graph, &P.graph0})
+            if (*g) {
+                (void)hipGraphDestroy(*g);
+                *g = nullptr;
+            }
+        capture(true, P.graph0, P.gexec0);
+        capture(false, P.graph, P.gexec);
         P.graph_iters = K;
         P.graph_stream = s;
         P.graph_tol = tol;
     }
+    const size_t sc_off = (sizeof(Ctl) + 255) / 256 * 256;
+    const size_t state_bytes = sc_off + (size_t)P.nsys * sizeof(SysCtl);
+    if (P.h_state_bytes < state_bytes) {
+        if (P.h_state) (void)hipHostFree(P.h_state);
+        P.h_state = nullptr;
+        P.h_state_bytes = 0;
+        HIPCHK(hipHostMalloc(&P.h_state, state_bytes, hipHostMallocDefault));
+        P.h_state_bytes = state_bytes;
+    }
+    void* h_ctl = P.h_state;
+    void* h_sc = (char*)P.h_state + sc_off;
     Ctl ctl{};
     SolveResult r;
     r.sc.resize(P.nsys);
     int launched = 0;
     for (;;) {
-        HIPCHK(hipGraphLaunch(P.gexec, s));
+        HIPCHK(hipGraphLaunch(launched == 0 ? P.gexec0 : P.gexec, s));
         launched += K;
         // the control block and the per-system states come back behind one synchronization
-        HIPCHK(hipMemcpyAsync(&ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(r.sc.data(), P.d_sysctl.p, P.nsys * sizeof(SysCtl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h_ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipMemcpyAsync(h_sc, P.d_sysctl.p, P.nsys * sizeof(SysCtl), hipMemcpyDeviceToHost, s));
+        HIPCHK(hipEventRecord(e1, s));  // complete once this replay's state is back; the last one ends the timing
         HIPCHK(hipStreamSynchronize(s));
+        std::memcpy(&ctl, h_ctl, sizeof(Ctl));
+        std::memcpy(r.sc.data(), h_sc, P.nsys * sizeof(SysCtl));
         if (ctl.error || ctl.active == 0 || launched >= P.max_iter + K) break;
     }
-    HIPCHK(hipEventRecord(e1, s));
-    HIPCHK(hipEventSynchronize(e1));
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     r.ms = ms;

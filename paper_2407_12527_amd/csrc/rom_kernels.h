@@ -152,6 +152,10 @@ hipError_t launch_fill(void* p, int64_t n, bool fp64, double v, hipStream_t s);
 // S = q for every system of a plan (the first source of source iteration)
 hipError_t launch_init_source(const SystemDev* sys, const ProblemDev* probs, int nsys, int64_t max_cells, bool fp64,
                               const void* q, void* src, hipStream_t s);
+// phi = 0 over [0, phi_total), S = q and a reset of the per-system and control state, one launch
+hipError_t launch_init_state(const SystemDev* sys, const ProblemDev* probs, int nsys, int64_t max_cells, bool fp64,
+                             const void* q, void* src, void* phi, int64_t phi_total, SysCtl* sc, Ctl* ctl,
+                             hipStream_t s);
 hipError_t launch_moments(const MomentsArgs& a, bool fp64, hipStream_t s);
 hipError_t launch_finish_var(const double* m2, double* var, int64_t cells, int64_t t, hipStream_t s);
 hipError_t launch_contract(const ContractArgs& a, int kind, hipStream_t s);  // 0 bf16 MFMA, 1 fp32, 2 fp64

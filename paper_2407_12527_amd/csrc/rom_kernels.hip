@@ -454,31 +454,38 @@ __global__ void sweep_prologue_kernel(Ctl* ctl)
     }
 }
 
+// Per-system and control state at the start of a solve.
+__device__ __forceinline__ void reset_system(SysCtl& c)
+{
+    c.dmax_bits = 0ull;
+    c.pmax_bits = 0ull;
+    c.iter = 0;
+    c.state = 0;
+    c.grow = 0;
+    c.r = 1.0;
+    c.r_prev = 1.0;
+}
+
+__device__ __forceinline__ void reset_ctl(Ctl* ctl, int nsys)
+{
+    ctl->active = nsys;
+    ctl->error = 0;
+    ctl->sweeps = 0;
+    ctl->t_first = ~0ull;
+    ctl->t_last = 0ull;
+    ctl->sweep_ticks = 0ull;
+    ctl->t_mark = wall_clock64();
+    ctl->ticket = 0;
+    ctl->blocks_done = 0;
+    ctl->epoch += 1;
+}
+
 // Clear per-system state before a solve (graph-safe: a kernel, not a memset).
 __global__ void reset_systems_kernel(SysCtl* sc, int nsys, Ctl* ctl)
 {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s < nsys) {
-        sc[s].dmax_bits = 0ull;
-        sc[s].pmax_bits = 0ull;
-        sc[s].iter = 0;
-        sc[s].state = 0;
-        sc[s].grow = 0;
-        sc[s].r = 1.0;
-        sc[s].r_prev = 1.0;
-    }
-    if (s == 0) {
-        ctl->active = nsys;
-        ctl->error = 0;
-        ctl->sweeps = 0;
-        ctl->t_first = ~0ull;
-        ctl->t_last = 0ull;
-        ctl->sweep_ticks = 0ull;
-        ctl->t_mark = wall_clock64();
-        ctl->ticket = 0;
-        ctl->blocks_done = 0;
-        ctl->epoch += 1;
-    }
+    if (s < nsys) reset_system(sc[s]);
+    if (s == 0) reset_ctl(ctl, nsys);
 }
 
 template <typename T>
@@ -885,6 +892,43 @@ hipError_t launch_init_source(const SystemDev* sys, const ProblemDev* probs, int
         hipLaunchKernelGGL(init_source_kernel<double>, grid, dim3(256), 0, s, sys, probs, nsys, (const double*)q, (double*)src);
     else
         hipLaunchKernelGGL(init_source_kernel<float>, grid, dim3(256), 0, s, sys, probs, nsys, (const float*)q, (float*)src);
+    return hipGetLastError();
+}
+
+// The whole initial state of source iteration in one launch: phi = 0 over [0, phi_total), the
+// first source S = q of every system (grid.y strides over the systems, grid.x over each system's
+// cells), and the per-system and control state reset.  The three parts write disjoint memory.
+template <typename T>
+__global__ void init_state_kernel(const SystemDev* __restrict__ sys, const ProblemDev* __restrict__ probs, int nsys,
+                                  const T* __restrict__ q, T* __restrict__ src, T* __restrict__ phi, int64_t phi_total,
+                                  SysCtl* __restrict__ sc, Ctl* ctl)
+{
+    const int64_t nthreads = (int64_t)gridDim.x * gridDim.y * blockDim.x;
+    const int64_t gtid = ((int64_t)blockIdx.y * gridDim.x + blockIdx.x) * blockDim.x + threadIdx.x;
+    for (int64_t i = gtid; i < phi_total; i += nthreads) phi[i] = T(0);
+    for (int k = blockIdx.y; k < nsys; k += gridDim.y) {
+        const SystemDev& sd = sys[k];
+        const ProblemDev& pd = probs[sd.prob];
+        const int64_t cells = (int64_t)pd.nx * pd.ny;
+        for (int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; c < cells; c += (int64_t)gridDim.x * blockDim.x)
+            src[sd.src_off + c] = q[pd.field_off + c];
+        if (blockIdx.x == 0 && threadIdx.x == 0) reset_system(sc[k]);
+    }
+    if (gtid == 0) reset_ctl(ctl, nsys);
+}
+
+hipError_t launch_init_state(const SystemDev* sys, const ProblemDev* probs, int nsys, int64_t max_cells, bool fp64,
+                             const void* q, void* src, void* phi, int64_t phi_total, SysCtl* sc, Ctl* ctl, hipStream_t s)
+{
+    if (nsys < 0 || max_cells < 0 || phi_total < 0) return hipErrorInvalidValue;
+    const dim3 grid((unsigned)std::max<int64_t>(1, std::min<int64_t>((max_cells + 255) / 256, 1024)),
+                    (unsigned)std::max(1, std::min(nsys, 65535)));
+    if (fp64)
+        hipLaunchKernelGGL(init_state_kernel<double>, grid, dim3(256), 0, s, sys, probs, nsys, (const double*)q,
+                           (double*)src, (double*)phi, phi_total, sc, ctl);
+    else
+        hipLaunchKernelGGL(init_state_kernel<float>, grid, dim3(256), 0, s, sys, probs, nsys, (const float*)q,
+                           (float*)src, (float*)phi, phi_total, sc, ctl);
     return hipGetLastError();
 }
 
