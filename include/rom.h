@@ -21,8 +21,11 @@
  *   - input arrays are copied during the call; the caller keeps ownership;
  *   - cell arrays are [ny][nx] doubles, x fastest: cell (i, j) at j*nx + i;
  *   - ordinate arrays keep the caller's ordinate order; dirs is [n][3] = (c, s, zeta);
- *   - a handle owns its device memory and queues all work on its stream (default: a
- *     non-blocking stream of its own; rom_set_stream binds the caller's);
+ *   - a handle owns its device memory, taken from the allocator installed with
+ *     rom_set_allocator (default hipMalloc / hipFree), and queues all work on its stream
+ *     (default: a non-blocking stream of its own; rom_set_stream binds the caller's);
+ *   - process-wide state: the allocator hook, and a lock that the device-touching calls take
+ *     (below); autotuned sweep shapes are cached in the handle that led the solve;
  *   - a handle is not thread-safe; distinct handles may be used from different threads, and
  *     the calls that touch the device then run one at a time (a process-wide lock: the first
  *     solve of a shape captures a HIP graph, which HIP fails if another thread meanwhile issues
@@ -163,9 +166,11 @@ typedef struct {
 /* ---- lifetime ----------------------------------------------------------------------------- */
 
 /* Create a problem.  sigma_t, sigma_s, q are [cells] host arrays (sigma_t > 0,
- * 0 <= sigma_s < sigma_t, q >= 0, all finite: eq. (1.1)); inflow may be NULL (vacuum).  The
- * data are validated and copied; device memory is taken on the current HIP device at the first
- * solve.  *out receives the handle. */
+ * 0 <= sigma_s < sigma_t, q >= 0, all finite: eq. (1.1)); inflow may be NULL (vacuum).  The grid
+ * needs nx, ny >= 1, nx * ny < 2^31 and nx, ny < 2^24 (the sweeps' progress counters tag a column
+ * count of 24 bits with the sweep's epoch), else ROM_E_ARG.  The data are validated and copied;
+ * device memory is taken on the current HIP device at the first solve.  *out receives the
+ * handle. */
 int rom_create(const rom_grid* grid, const double* sigma_t, const double* sigma_s, const double* q,
                const rom_inflow* inflow, rom_handle** out);
 
@@ -174,6 +179,17 @@ void rom_destroy(rom_handle* h);
 
 /* Queue all later work of h on this HIP stream (a hipStream_t; NULL = null stream). */
 int rom_set_stream(rom_handle* h, void* hip_stream);
+
+/* Device allocator for every buffer librom takes afterwards (handle plans, ensemble moments, slab
+ * systems): alloc(bytes, ctx) returns device memory on the current HIP device, 256-byte aligned,
+ * that no queued device work still uses (or NULL: the call that needed it fails with
+ * ROM_E_NOMEM); free_fn(ptr, ctx) takes it back.  librom waits for the device to go idle before
+ * it calls free_fn, as hipFree would.  alloc and free_fn both NULL restore hipMalloc / hipFree;
+ * exactly one NULL is ROM_E_ARG.  Blocks already taken are returned to the allocator that gave
+ * them.  This hook is the way a framework lends librom its memory pool (the Python binding
+ * installs PyTorch's caching allocator); it is process-wide, and changing it while another
+ * thread is inside librom is safe (the call takes the device lock). */
+int rom_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(void* ptr, void* ctx), void* ctx);
 
 /* Set the ordinate set: dirs [n][3] (c, s, zeta) with c^2 + s^2 + zeta^2 = 1 (to 1e-12) and
  * weights w [n] summing to 1 (to 1e-12), as DOM requires after the Sec. 2 system.  Ordinates are

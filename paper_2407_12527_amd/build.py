@@ -38,9 +38,19 @@ def _run(cmd):
     return out
 
 
-def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+def _stale(src: str, obj: str) -> bool:
+    """An object is stale when it is missing or older than its source or any header of csrc/."""
+    if not os.path.exists(obj):
+        return True
+    t = os.path.getmtime(obj)
+    deps = [src] + [os.path.join(CSRC, h) for h in os.listdir(CSRC) if h.endswith(".h")]
+    return any(os.path.getmtime(d) > t for d in deps)
+
+
+def build(verbose: bool = False, out: str = LIB, defines=(), incremental: bool = False) -> str:
     """Compile every source under csrc/ and link `out` (default: the in-tree librom.so).
-    `defines` are extra -D flags for the device sources (build variants for A/B timing)."""
+    `defines` are extra -D flags for the device sources (build variants for A/B timing);
+    `incremental` recompiles only sources whose objects are stale."""
     build_dir = BUILD if not defines else BUILD + "_" + "_".join(d.replace("=", "") for d in defines)
     os.makedirs(build_dir, exist_ok=True)
     hipcc = _hipcc()
@@ -50,13 +60,15 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
         path = os.path.join(CSRC, src)
         obj = os.path.join(build_dir, src + ".o")
         if src.endswith(".hip"):
-            jobs.append([hipcc, *DEVICE_FLAGS, *[f"-D{d}" for d in defines], "-c", path, "-o", obj])
+            cmd = [hipcc, *DEVICE_FLAGS, *[f"-D{d}" for d in defines], "-c", path, "-o", obj]
         elif src.endswith(".cpp"):
-            jobs.append([hipcc, *HOST_FLAGS, "-c", path, "-o", obj])
+            cmd = [hipcc, *HOST_FLAGS, "-c", path, "-o", obj]
         else:
             continue
         objs.append(obj)
-    with cf.ThreadPoolExecutor(max_workers=min(8, len(jobs))) as ex:
+        if not incremental or _stale(path, obj):
+            jobs.append(cmd)
+    with cf.ThreadPoolExecutor(max_workers=max(1, min(8, len(jobs)))) as ex:
         for log in ex.map(_run, jobs):
             if verbose and log.strip():
                 print(log)
@@ -67,4 +79,4 @@ def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
 
 
 if __name__ == "__main__":
-    print(build(verbose="-v" in sys.argv))
+    print(build(verbose="-v" in sys.argv, incremental="--incremental" in sys.argv))

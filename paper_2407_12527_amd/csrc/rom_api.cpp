@@ -40,23 +40,65 @@ std::recursive_mutex& api_mutex()
 }
 #define ROM_API_LOCK std::lock_guard<std::recursive_mutex> rom_api_lock_(api_mutex())
 
+// Device allocator of every handle and plan buffer: hipMalloc / hipFree unless the caller
+// installed a hook with rom_set_allocator (the only process-wide state the boundary keeps).
+struct AllocHook {
+    void* (*alloc)(size_t, void*) = nullptr;
+    void (*free)(void*, void*) = nullptr;
+    void* ctx = nullptr;
+};
+AllocHook& alloc_hook()
+{
+    static AllocHook hook;
+    return hook;
+}
+
 struct DevMem {
     void* p = nullptr;
     size_t bytes = 0;
+    // the hook that gave this block (NULL: hipMalloc); a block is returned to its own allocator
+    // even when the hook has been changed since
+    void (*freefn)(void*, void*) = nullptr;
+    void* fctx = nullptr;
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
     ~DevMem() { release(); }
     void release()
     {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (freefn) {
+                // hipFree waits for the device; a hook gets the same guarantee: no queued work
+                // still uses the block when its allocator may hand it out again
+                (void)hipDeviceSynchronize();
+                freefn(p, fctx);
+            } else {
+                (void)hipFree(p);
+            }
+        }
         p = nullptr;
         bytes = 0;
+        freefn = nullptr;
+        fctx = nullptr;
     }
     hipError_t alloc(size_t n)
     {
         release();
         if (n == 0) n = 256;
+        const AllocHook hook = alloc_hook();
+        if (hook.alloc) {
+            p = hook.alloc(n, hook.ctx);
+            if (!p) return hipErrorOutOfMemory;
+            if (((uintptr_t)p & 255) != 0) {  // kernels issue 16-byte loads from 256-byte-aligned pools
+                hook.free(p, hook.ctx);
+                p = nullptr;
+                return hipErrorInvalidValue;
+            }
+            freefn = hook.free;
+            fctx = hook.ctx;
+            bytes = n;
+            return hipSuccess;
+        }
         hipError_t e = hipMalloc(&p, n);
         if (e == hipSuccess) bytes = n;
         else p = nullptr;
@@ -147,6 +189,9 @@ struct rom_handle {
     std::unique_ptr<Plan> ens_plan, batch_plan;
     std::string ens_key, batch_key, batch_versions;
     uint64_t uid = next_uid();
+    // autotuner choices of the batch shapes this handle led (key -> sweep, tile x, tile y, band,
+    // rows, ordinates per lane), kept with the handle rather than process-wide
+    std::map<std::string, std::array<int, 6>> tune_cache;
     // device-resident result of the last solve
     const void* res_dev = nullptr;
     bool res_fp64 = false;
@@ -1473,6 +1518,8 @@ int rom_create(const rom_grid* grid, const double* sigma_t, const double* sigma_
     if (!grid || !sigma_t || !sigma_s || !q) return fail(nullptr, ROM_E_ARG, "NULL grid or field");
     if (grid->nx <= 0 || grid->ny <= 0) return fail(nullptr, ROM_E_ARG, "nx, ny must be positive");
     if ((int64_t)grid->nx * grid->ny >= (int64_t)1 << 31) return fail(nullptr, ROM_E_ARG, "grid too large (2^31 cells or more)");
+    // the sweeps publish (epoch << 24) | columns done in their progress counters
+    if (grid->nx >= (1 << 24) || grid->ny >= (1 << 24)) return fail(nullptr, ROM_E_ARG, "nx and ny must be below 2^24");
     if (!isfin(grid->x0) || !isfin(grid->x1) || !isfin(grid->y0) || !isfin(grid->y1) || !(grid->x1 > grid->x0) ||
         !(grid->y1 > grid->y0))
         return fail(nullptr, ROM_E_ARG, "grid box must satisfy x1 > x0, y1 > y0");
@@ -1525,6 +1572,17 @@ int rom_set_stream(rom_handle* h, void* stream)
 {
     if (!h) return ROM_E_ARG;
     h->user_stream = (hipStream_t)stream;
+    return ROM_OK;
+}
+
+int rom_set_allocator(void* (*alloc)(size_t, void*), void (*free_fn)(void*, void*), void* ctx)
+{
+    ROM_API_LOCK;
+    if ((alloc == nullptr) != (free_fn == nullptr)) return fail(nullptr, ROM_E_ARG, "alloc and free must both be set or both be NULL");
+    AllocHook& hook = alloc_hook();
+    hook.alloc = alloc;
+    hook.free = free_fn;
+    hook.ctx = alloc ? ctx : nullptr;
     return ROM_OK;
 }
 
@@ -1609,6 +1667,7 @@ int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double
     rom_si_opts o;
     int rc = validate_opts(h, opts, o);
     if (rc) return rc;
+    h->res_dev = nullptr;  // the plan that held the last result may be released below
     try {
         const bool per = src_per_ordinate != 0;
         const size_t nsrc = per ? (size_t)h->n * h->cells : (size_t)h->cells;
@@ -1701,7 +1760,8 @@ bool is_aniso(const rom_handle* h) { return scat_mode(h) == 2; }
 // and occupancy, and the best choice depends on the batch: a single problem with few ordinates
 // wants the row-lane kernel's spatial parallelism, a large ensemble the strip kernel's in-lane
 // ordinate sums.  The first solve of a batch shape times each candidate on the real buffers (one
-// warm-up and two timed sweeps each) and caches the fastest for the process.  Every choice is
+// warm-up and five timed steps each) and caches the fastest in the handle that leads the solve
+// (the ensemble's or single solve's handle, a batch's first handle).  Every choice is
 // deterministic; strip tiles and bands give bitwise identical results, while the row-lane kernel
 // sums the ordinates of a cell in another (fixed) order.
 std::string tune_key(const std::vector<SysInput>& in, const rom_si_opts& o, int smode)
@@ -1746,21 +1806,17 @@ void apply_choice(const TuneChoice& c, rom_si_opts& o)
 }
 
 // Time sweep + combine steps of every candidate on the real buffers of this batch shape (zero
-// sources) and keep the fastest for the process.  Candidates: the strip kernel's tiles x bands, and, for
-// isotropic step-scheme problems, the row-lane kernel's (rows, ordinates per lane).
-void autotune(std::vector<SysInput>& in, rom_si_opts& o, int smode, hipStream_t s)
+// sources) and keep the fastest in the owner handle's cache.  Candidates: the strip kernel's tiles x
+// bands, and, for isotropic step-scheme problems, the row-lane kernel's (rows, ordinates per lane).
+void autotune(rom_handle* owner, std::vector<SysInput>& in, rom_si_opts& o, int smode, hipStream_t s)
 {
-    // process-wide choices; the lock covers the lookup and the insertion, not the timing runs (two
-    // threads tuning the same shape at once both measure, the later insertion wins)
-    static std::map<std::string, TuneChoice> cache;
-    static std::mutex cache_mu;
     const bool aniso = smode == 2;
     const std::string key = tune_key(in, o, smode);
     {
-        std::lock_guard<std::mutex> lk(cache_mu);
-        auto it = cache.find(key);
-        if (it != cache.end()) {
-            apply_choice(it->second, o);
+        auto it = owner->tune_cache.find(key);
+        if (it != owner->tune_cache.end()) {
+            const auto& v = it->second;
+            apply_choice(TuneChoice{v[0], v[1], v[2], v[3], v[4], v[5]}, o);
             return;
         }
     }
@@ -1831,10 +1887,7 @@ void autotune(std::vector<SysInput>& in, rom_si_opts& o, int smode, hipStream_t 
     }
     for (auto& e : ev) (void)hipEventDestroy(e);
     if (pick.sweep == 0) return;  // nothing measurable: keep the heuristic
-    {
-        std::lock_guard<std::mutex> lk(cache_mu);
-        cache[key] = pick;
-    }
+    owner->tune_cache[key] = {pick.sweep, pick.tx, pick.ty, pick.band, pick.rows, pick.k};
     apply_choice(pick, o);
 }
 
@@ -1853,7 +1906,7 @@ int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opt
     if (reuse == 0 || !slot) {
         const bool free_shape = o.sweep == ROM_SWEEP_DIAG ? (o.diag_rows == 0 || o.diag_k == 0 || o.band == 0)
                                                           : (o.tile_x == 0 && o.band == 0);
-        if (free_shape && autotune_enabled()) autotune(in, o, smode, owner->stream());
+        if (free_shape && autotune_enabled()) autotune(owner, in, o, smode, owner->stream());
         slot.reset(new Plan());
         build_plan(*slot, in, o, smode, o.max_iter);
         if (aniso) {
@@ -1970,6 +2023,7 @@ int rom_source_iterate(rom_handle* h, const rom_si_opts* opts, double* phi, rom_
     rom_si_opts o;
     int rc = validate_opts(h, opts, o);
     if (rc) return rc;
+    h->res_dev = nullptr;  // set again only when this solve succeeds
     try {
         std::vector<SysInput> in{{h, h->dirs.data(), h->w.data(), h->n, true}};
         const std::string sig = plan_signature(o, scat_sig(h), 0, 1);
@@ -2027,6 +2081,7 @@ int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, d
     rom_si_opts o;
     int rc = validate_opts(h0, opts, o);
     if (rc) return rc;
+    h0->res_dev = nullptr;  // a batch leaves no single result on its first handle
     try {
         std::vector<SysInput> in;
         for (int i = 0; i < k; ++i) in.push_back({hs[i], hs[i]->dirs.data(), hs[i]->w.data(), hs[i]->n, true});
@@ -2085,6 +2140,7 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
     rom_si_opts o;
     int rc = check_ensemble(h, *spec, opts, o);
     if (rc) return rc;
+    h->res_dev = nullptr;  // the moment buffers and plans are reallocated below
     try {
         hipStream_t s = h->stream();
         HIPCHK(h->ens_mean.alloc(h->cells * 8));
@@ -2135,6 +2191,7 @@ int rom_ensemble_samples(rom_handle* h, int32_t t, uint64_t seed, int64_t first,
     rom_si_opts o;
     int rc = check_ensemble(h, *spec, opts, o);
     if (rc) return rc;
+    h->res_dev = nullptr;
     try {
         EnsAgg ag;
         auto download = [&](Plan& P, int done, int b) {

@@ -3,13 +3,17 @@
 Every compute step runs in librom's gfx950 kernels.  The raw functions ``rom_*`` take and return
 exactly what the C functions do (numpy arrays are passed as host pointers); ``Handle`` wraps a
 ``rom_handle*`` with numpy-friendly methods and raises ``RomError`` on negative status codes.
-PyTorch is used only to hand librom a HIP stream (``Handle.use_torch_stream``) and to view
+PyTorch is used only for device memory and streams: its caching allocator is installed as
+librom's device allocator (``use_torch_allocator``, done when the first handle is created on a
+machine with a GPU), it can hand librom a HIP stream (``Handle.use_torch_stream``), and it views
 device-resident results (``Handle.phi_device_tensor``).
 """
 from __future__ import annotations
 
+import atexit
 import ctypes as C
 import os
+import weakref
 
 import numpy as np
 
@@ -25,7 +29,7 @@ __all__ = [
     "rom_ensemble_samples", "rom_solve_batch", "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
     "rom_last_error", "rom_version", "rom_slab_create", "rom_slab_destroy", "rom_slab_set_stream", "rom_slab_solve",
     "rom_slab_ordinates", "rom_slab_last_error", "ROM_SLAB_RANDOM", "ROM_SLAB_GAUSS", "ROM_SLAB_UNIFORM", "Slab",
-    "slab_ordinates",
+    "slab_ordinates", "rom_set_allocator", "use_torch_allocator", "use_hip_allocator",
 ]
 
 ROM_OK, ROM_NOT_CONVERGED = 0, 1
@@ -41,7 +45,7 @@ ROM_FACE_LEFT, ROM_FACE_RIGHT, ROM_FACE_BOTTOM, ROM_FACE_TOP = 0, 1, 2, 3
 ROM_SLAB_RANDOM, ROM_SLAB_GAUSS, ROM_SLAB_UNIFORM = 0, 1, 2
 
 # every function declared in include/rom.h
-EXPORTS = ("rom_create", "rom_destroy", "rom_set_stream", "rom_set_ordinates", "rom_set_inflow_angular",
+EXPORTS = ("rom_create", "rom_destroy", "rom_set_stream", "rom_set_allocator", "rom_set_ordinates", "rom_set_inflow_angular",
            "rom_set_scattering", "rom_sweep", "rom_source_iterate", "rom_ensemble", "rom_ensemble_samples",
            "rom_solve_batch",
            "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
@@ -92,6 +96,10 @@ def library_path() -> str:
 
 _lib = None
 
+# rom_set_allocator's callback types: void* alloc(size_t bytes, void* ctx), void free(void* p, void* ctx)
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
 
 def lib():
     """Load librom.so (built in-tree by ``build.py``).  Raises if it is missing: there is no
@@ -108,6 +116,7 @@ def lib():
         L.rom_destroy.argtypes = [P]
         L.rom_destroy.restype = None
         L.rom_set_stream.argtypes = [P, P]
+        L.rom_set_allocator.argtypes = [_ALLOC_FN, _FREE_FN, P]
         L.rom_set_ordinates.argtypes = [P, C.c_int32, P, P]
         L.rom_set_inflow_angular.argtypes = [P, C.c_int32, P]
         L.rom_set_scattering.argtypes = [P, C.c_int32, C.c_double, P]
@@ -152,6 +161,10 @@ def rom_destroy(h):
 
 def rom_set_stream(h, stream):
     return lib().rom_set_stream(h, stream)
+
+
+def rom_set_allocator(alloc, free, ctx):
+    return lib().rom_set_allocator(alloc, free, ctx)
 
 
 def rom_set_ordinates(h, n, dirs, w):
@@ -258,6 +271,74 @@ def _check(st, h=None):
     return st
 
 
+# ------------------------------------------------------------------ device memory from PyTorch
+_allocator = None      # (alloc callback, free callback) kept alive while installed
+_live = weakref.WeakSet()  # handles and slabs to release before the interpreter tears torch down
+
+
+def use_torch_allocator():
+    """Make PyTorch's caching allocator librom's device allocator (rom_set_allocator).  A block
+    is taken on the current device and stream after that stream has drained, so no queued torch
+    work still uses it; librom waits for the device before it gives a block back."""
+    global _allocator
+    import torch
+
+    def _alloc(nbytes, ctx):
+        try:
+            dev = torch.cuda.current_device()
+            stream = torch.cuda.current_stream(dev)
+            ptr = torch.cuda.caching_allocator_alloc(int(nbytes), dev, stream)
+            stream.synchronize()
+            return ptr
+        except Exception:  # out of memory: librom reports ROM_E_NOMEM
+            return None
+
+    def _free(ptr, ctx):
+        torch.cuda.caching_allocator_delete(ptr)
+
+    cbs = (_ALLOC_FN(_alloc), _FREE_FN(_free))
+    _check(lib().rom_set_allocator(cbs[0], cbs[1], None))
+    _allocator = cbs
+
+
+def use_hip_allocator():
+    """Restore librom's own hipMalloc / hipFree for blocks taken from now on."""
+    global _allocator
+    _check(lib().rom_set_allocator(_ALLOC_FN(), _FREE_FN(), None))
+    # blocks taken from torch are still returned through its callbacks: keep them alive
+    if _allocator is not None:
+        _retired.append(_allocator)
+    _allocator = None
+
+
+_retired = []
+_allocator_checked = False
+
+
+def _default_allocator():
+    """Install torch's allocator once, on the first handle, when a GPU is there."""
+    global _allocator_checked
+    if _allocator_checked:
+        return
+    _allocator_checked = True
+    try:
+        import torch
+        if torch.cuda.is_available():
+            use_torch_allocator()
+    except ImportError:
+        pass
+
+
+@atexit.register
+def _release_all():
+    # handles still alive at exit give their device memory back while torch is still usable
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
 def si_opts(tol=1e-6, max_iter=1000, precision=ROM_PREC_FP32, scheme=ROM_SCHEME_STEP, iters_per_check=0,
             tile=(0, 0), contract_split=0, band=0, sweep=0, diag_rows=0, diag_k=0) -> rom_si_opts:
     o = rom_si_opts()
@@ -295,6 +376,7 @@ class Handle:
     """Owns one ``rom_handle*`` (a problem on the current HIP device)."""
 
     def __init__(self, nx, ny, sigma_t, sigma_s, q, box=(0.0, 1.0, 0.0, 1.0), inflow=None):
+        _default_allocator()
         cells = nx * ny
         self.nx, self.ny, self.cells = int(nx), int(ny), cells
         self._keep = []
@@ -313,6 +395,7 @@ class Handle:
         _check(lib().rom_create(C.byref(g), _ptr(st), _ptr(ss), _ptr(qq), C.byref(fin) if fin else None, C.byref(h)))
         self.h = h
         self.n = 0
+        _live.add(self)
 
     def close(self):
         if getattr(self, "h", None):
@@ -436,6 +519,7 @@ class Slab:
     """Owns one ``rom_slab*``: a slab problem with fields at the nx + 1 grid points."""
 
     def __init__(self, nx, sigma_t, sigma_s, q, x0=0.0, x1=1.0):
+        _default_allocator()
         self.nx = int(nx)
         self.s = None
         out = C.c_void_p()
@@ -444,6 +528,7 @@ class Slab:
         if rc != ROM_OK:
             raise RomError(rc, (lib().rom_slab_last_error(None) or b"").decode())
         self.s = out.value
+        _live.add(self)
 
     def close(self):
         if self.s:

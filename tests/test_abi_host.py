@@ -81,7 +81,7 @@ def _create(R, st, ss, q, nx=4, ny=3, inflow=None, grid=None):
 
 @pytest.mark.parametrize("case,code", [
     ("sigma_t_zero", -2), ("sigma_s_neg", -2), ("sigma_s_ge_sigma_t", -2), ("q_neg", -2), ("nan", -2),
-    ("nx_zero", -1), ("box", -1), ("inflow_neg", -2), ("cells_2_31", -1)])
+    ("nx_zero", -1), ("box", -1), ("inflow_neg", -2), ("cells_2_31", -1), ("nx_2_24", -1), ("ny_2_24", -1)])
 def test_create_rejects_bad_input(R, case, code):
     cells = 12
     st, ss, q = np.ones(cells), np.full(cells, 0.5), np.ones(cells)
@@ -105,6 +105,12 @@ def test_create_rejects_bad_input(R, case, code):
     elif case == "cells_2_31":
         # refused on the size alone, before the (12-cell) field arrays are read
         grid = R.rom_grid(65536, 32768, 0.0, 1.0, 0.0, 1.0)
+    elif case == "nx_2_24":
+        # 2^24 x 64 cells is below 2^31, but a column count of 2^24 would overflow the 24-bit
+        # count the sweeps tag with their epoch in the progress counters
+        grid = R.rom_grid(1 << 24, 64, 0.0, 1.0, 0.0, 1.0)
+    elif case == "ny_2_24":
+        grid = R.rom_grid(64, 1 << 24, 0.0, 1.0, 0.0, 1.0)
     elif case == "inflow_neg":
         keep = np.array([1.0, -1.0, 0.0])
         inflow = R.rom_inflow(keep.ctypes.data, None, None, None)
@@ -252,3 +258,15 @@ def test_empty_counts_are_refused(R):
         rc = R.lib().rom_slab_solve(s.s, t, n, mu.ctypes.data, w.ctypes.data, inflow.ctypes.data, None,
                                     phis.ctypes.data, it.ctypes.data, Cc.byref(st))
         assert rc == R.ROM_E_ARG, (t, n)
+
+
+def test_set_allocator_arguments(R):
+    """The allocator hook takes both callbacks or neither; installing and removing it needs no
+    device (the hook is called only when a solve takes device memory)."""
+    noop_alloc = R._ALLOC_FN(lambda n, ctx: None)
+    noop_free = R._FREE_FN(lambda p, ctx: None)
+    assert R.rom_set_allocator(noop_alloc, R._FREE_FN(), None) == R.ROM_E_ARG
+    assert R.rom_set_allocator(R._ALLOC_FN(), noop_free, None) == R.ROM_E_ARG
+    assert len(R.rom_last_error(None)) > 0
+    assert R.rom_set_allocator(noop_alloc, noop_free, None) == R.ROM_OK
+    assert R.rom_set_allocator(R._ALLOC_FN(), R._FREE_FN(), None) == R.ROM_OK

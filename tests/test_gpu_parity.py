@@ -1,18 +1,26 @@
 """GPU parity: librom's HIP path (through the C ABI) against the FP64 CPU oracle on the same
 seeded inputs and bit-identical ordinate sets.
 
-Tolerances (normwise, over all cells: ||phi_gpu - phi_oracle||_2 / ||phi_oracle||_2):
-  * FP32 sweeps: 1e-5;  FP64 path: 1e-11 at a fixed iteration count, 1e-9 when both sides stop on
-    the same tolerance;
+Every comparison is element-wise (tests/parity.py): the normwise figure
+||phi_gpu - phi_oracle||_2 / ||phi_oracle||_2, the max-norm figure max|dphi| / max|phi_oracle|
+(both at the bar), and the relative error of every cell whose flux is at least 1e-3 of the
+maximum (at ten times the bar).  Bars:
+  * FP32 sweeps: 1e-5 (a single sweep 1e-6..2e-6);  FP64 path: 1e-11 at a fixed iteration count,
+    1e-9 when both sides stop on the same tolerance;
   * BF16 contraction (anisotropic FP32 path): 2e-3;
-  * ensemble variance (a difference of nearly equal per-sample fluxes): 2e-3 normwise for FP32.
-Pointwise relative errors are not used: behind thick absorbers phi spans many decades.
+  * FP32 ensemble variance: 1e-5 (per cell 1e-4).
+Tolerance-stopped solves are compared at the GPU's iteration count.  Cells in deep shadow (below
+1e-3 of the maximum: behind thick absorbers the flux spans many decades) are held by the max-norm
+figure only.
 """
 import ctypes as C
 import math
 
 import numpy as np
 import pytest
+
+import parity
+from parity import nrm
 
 import rom_inputs as RI
 
@@ -27,10 +35,6 @@ def R():
     from paper_2407_12527_amd import rom
     rom.lib()
     return rom
-
-
-def nrm(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
 def rand_problem(rng, nx, ny, ratio=0.9):
@@ -72,8 +76,8 @@ def test_sweep_isotropic_source(R, orc, prec, tile, spec):
     psi_ref = orc.sweep(p, d, S)
     phi_ref = orc.scalar_flux(w, psi_ref)
     tol = 1e-12 if prec == "fp64" else 1e-6
-    assert nrm(phi, phi_ref) < tol
-    assert nrm(psi, psi_ref) < (1e-12 if prec == "fp64" else 2e-6)
+    parity.check(phi, phi_ref, tol)
+    parity.check(psi, psi_ref, (1e-12 if prec == "fp64" else 2e-6))
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -94,8 +98,8 @@ def test_sweep_per_ordinate_source_and_angular_inflow(R, orc, prec):
     phi, psi = h.sweep(S, o, want_psi=True)
     psi_ref = orc.sweep(p, d, S)
     tol = 1e-12 if prec == "fp64" else 2e-6
-    assert nrm(psi, psi_ref) < tol
-    assert nrm(phi, orc.scalar_flux(w, psi_ref)) < tol
+    parity.check(psi, psi_ref, tol)
+    parity.check(phi, orc.scalar_flux(w, psi_ref), tol)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -110,7 +114,7 @@ def test_sweep_diamond_difference(R, orc, prec):
     o = R.si_opts(precision=R.ROM_PREC_FP64 if prec == "fp64" else R.ROM_PREC_FP32, scheme=R.ROM_SCHEME_DD)
     phi = h.sweep(S, o)
     ref = orc.scalar_flux(w, orc.sweep(p, d, S, scheme=orc.SCHEME_DD))
-    assert nrm(phi, ref) < (1e-12 if prec == "fp64" else 1e-5)
+    parity.check(phi, ref, (1e-12 if prec == "fp64" else 1e-5))
 
 
 @pytest.mark.parametrize("shape", [(1, 1), (1, 17), (23, 1), (5, 3)])
@@ -123,7 +127,7 @@ def test_sweep_degenerate_grids(R, orc, shape):
     h.set_ordinates(d, w)
     S = rng.uniform(0, 1, nx * ny)
     phi = h.sweep(S, R.si_opts(precision=R.ROM_PREC_FP64))
-    assert nrm(phi, orc.scalar_flux(w, orc.sweep(p, d, S))) < 1e-13
+    parity.check(phi, orc.scalar_flux(w, orc.sweep(p, d, S)), 1e-13)
 
 
 def test_single_ordinate(R, orc):
@@ -136,7 +140,7 @@ def test_single_ordinate(R, orc):
     phi, st_, rc = h.source_iterate(R.si_opts(precision=R.ROM_PREC_FP64, tol=1e-12))
     ref = orc.source_iterate(p, d, w, None, tol=1e-12)
     assert rc == 0 and st_.iters == ref["iters"]
-    assert nrm(phi, ref["phi"]) < 1e-13
+    parity.check(phi, ref["phi"], 1e-13)
 
 
 # ------------------------------------------------------------------------------------ source iteration
@@ -151,11 +155,11 @@ def test_si_c1_fp64(R, orc):
     phi, st, rc = h.source_iterate(R.si_opts(tol=-1.0, max_iter=6, precision=R.ROM_PREC_FP64))
     ref = orc.source_iterate(p, d, w, None, tol=0.0, max_iter=6)
     assert rc == R.ROM_NOT_CONVERGED and st.iters == 6
-    assert nrm(phi, ref["phi"]) < 1e-11
+    parity.check(phi, ref["phi"], 1e-11)
     phi, st, rc = h.source_iterate(R.si_opts(tol=1e-8, precision=R.ROM_PREC_FP64))
     ref = orc.source_iterate(p, d, w, None, tol=1e-8)
     assert rc == 0 and st.iters == ref["iters"]
-    assert nrm(phi, ref["phi"]) < 1e-9
+    parity.check(phi, ref["phi"], 1e-9)
     assert st.updates == ref["iters"] * 4096 * 32
 
 
@@ -167,9 +171,8 @@ def test_si_c2_full_size(R, orc):
     d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 8, 8, seed=0)
     h.set_ordinates(d, w)
     phi, st, rc = h.source_iterate(R.si_opts(tol=1e-6))
-    ref = orc.source_iterate(p, d, w, None, tol=1e-6)
-    assert rc == 0 and abs(st.iters - ref["iters"]) <= 1
-    assert nrm(phi, ref["phi"]) < 1e-5
+    assert rc == 0
+    parity.si_check(orc, p, d, w, None, phi, st.iters, 1e-6, 1e-5, what="c2")
     # the checkerboard and the stratified set are mirror symmetric
     P = phi.reshape(256, 256)
     assert nrm(P[:, ::-1], P) < 1e-6 and nrm(P[::-1, :], P) < 1e-6
@@ -189,7 +192,7 @@ def test_si_fp32_fixed_iterations(R, orc, tile):
     phi, stt, rc = h.source_iterate(R.si_opts(tol=-1.0, max_iter=9, tile=tile))
     ref = orc.source_iterate(p, d, w, None, tol=0.0, max_iter=9)
     assert rc == R.ROM_NOT_CONVERGED and stt.iters == 9
-    assert nrm(phi, ref["phi"]) < 1e-5
+    parity.check(phi, ref["phi"], 1e-5)
 
 
 def test_si_zero_source_and_not_converged(R, orc):
@@ -230,9 +233,8 @@ def test_si_anisotropic_hg(R, orc, prec):
     W = orc.build_W(d, w, orc.SCAT_HG, 0.8, fold=1)
     o = R.si_opts(tol=1e-7, precision=R.ROM_PREC_FP64 if prec == "fp64" else R.ROM_PREC_FP32)
     phi, st, rc = h.source_iterate(o)
-    ref = orc.source_iterate(p, d, w, W, tol=1e-7)
     assert rc == 0
-    assert nrm(phi, ref["phi"]) < (1e-9 if prec == "fp64" else 2e-3)
+    parity.si_check(orc, p, d, w, W, phi, st.iters, 1e-7, 1e-9 if prec == "fp64" else 2e-3)
 
 
 def test_si_anisotropic_dense_fixed_iterations_fp64(R, orc):
@@ -249,7 +251,7 @@ def test_si_anisotropic_dense_fixed_iterations_fp64(R, orc):
     W = orc.build_W(d, w, orc.SCAT_DENSE, P=P)
     phi, st_, rc = h.source_iterate(R.si_opts(tol=-1.0, max_iter=5, precision=R.ROM_PREC_FP64))
     ref = orc.source_iterate(p, d, w, W, tol=0.0, max_iter=5)
-    assert nrm(phi, ref["phi"]) < 1e-12
+    parity.check(phi, ref["phi"], 1e-12)
 
 
 # ------------------------------------------------------------------------------------ ensemble / batch
@@ -265,25 +267,28 @@ def test_ensemble_mean_var(R, orc, prec):
     mean, var, st, rc = h.ensemble(t, 7, R.ROM_ORD_STRATIFIED, 4, 8, o)
     ref = orc.ensemble(p, orc.ORD_STRATIFIED, 4, 8, 7, t, tol=1e-7)
     assert rc == 0 and st.samples == t
-    assert nrm(mean, ref["mean"]) < (1e-10 if prec == "fp64" else 1e-5)
-    assert nrm(var, ref["var"]) < (1e-8 if prec == "fp64" else 2e-3)
+    parity.check(mean, ref["mean"], (1e-10 if prec == "fp64" else 1e-5))
+    # the variance is formed in FP64 from FP32 per-sample fluxes whose relative error is ~1e-6;
+    # their spread phi_s - mean is a few per cent of phi here, so the variance carries about
+    # 2e-6 / 0.03 ~ 1e-4 relative error at most and ~1e-6 normwise (measured 4e-7): the FP32 bar
+    parity.check(var, ref["var"], 1e-8 if prec == "fp64" else 1e-5, cell_tol=1e-7 if prec == "fp64" else 1e-4)
     assert st.min_iters == int(ref["iters"].min()) or prec == "fp32"
 
 
 def test_batch_uneven_problems(R, orc):
     wl = RI.c5(count=5, sides=(16, 24, 40), m_range=(4, 20))
-    hs, refs = [], []
+    hs, cases = [], []
     for k, f in enumerate(wl.fields):
         h, p = both(R, orc, f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
         nz, nt = orc.stratified_spec(wl.n_ord[k])
         d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, nz, nt, seed=wl.problem_seed(k))
         h.set_ordinates(d, w)
         hs.append(h)
-        refs.append(orc.source_iterate(p, d, w, None, tol=1e-6)["phi"])
+        cases.append((p, d, w))
     outs, stats, rc = R.solve_batch(hs, R.si_opts(tol=1e-6))
     assert rc == 0
-    for o_, r_ in zip(outs, refs):
-        assert nrm(o_, r_) < 1e-5
+    for k, (o_, (p, d, w)) in enumerate(zip(outs, cases)):
+        parity.si_check(orc, p, d, w, None, o_, stats[k].iters, 1e-6, 1e-5, what=str(k))
 
 
 def test_batch_without_download_then_with(R, orc):
@@ -291,22 +296,22 @@ def test_batch_without_download_then_with(R, orc):
     one that downloads them, and the following downloading solve (plan reused, first sources set
     again by the one-launch initialization) still matches the oracle."""
     wl = RI.c5(count=4, sides=(16, 32), m_range=(4, 12))
-    hs, refs = [], []
+    hs, cases = [], []
     for k, f in enumerate(wl.fields):
         h, p = both(R, orc, f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
         nz, nt = orc.stratified_spec(wl.n_ord[k])
         d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, nz, nt, seed=wl.problem_seed(k))
         h.set_ordinates(d, w)
         hs.append(h)
-        refs.append(orc.source_iterate(p, d, w, None, tol=1e-6))
+        cases.append((p, d, w))
     o = R.si_opts(tol=1e-6)
     outs0, st0, rc0 = R.solve_batch(hs, o, download=False)
     assert rc0 == 0 and outs0 == [None] * len(hs)
     outs1, st1, rc1 = R.solve_batch(hs, o)
     assert rc1 == 0
-    for a, b, o_, r_ in zip(st0, st1, outs1, refs):
-        assert a.iters == b.iters and abs(b.iters - r_["iters"]) <= 1
-        assert nrm(o_, r_["phi"]) < 1e-5
+    for a, b, o_, (p, d, w) in zip(st0, st1, outs1, cases):
+        assert a.iters == b.iters
+        parity.si_check(orc, p, d, w, None, o_, b.iters, 1e-6, 1e-5)
 
 
 def test_si_near_critical_many_replays(R, orc):
@@ -323,6 +328,6 @@ def test_si_near_critical_many_replays(R, orc):
     phi, st, rc = h.source_iterate(o)
     ref = orc.source_iterate(p, d, w, None, tol=1e-8, max_iter=5000)
     assert rc == 0 and st.iters > 300 and abs(st.iters - ref["iters"]) <= 1
-    assert nrm(phi, ref["phi"]) < (1e-10 if st.iters == ref["iters"] else 1e-7)
+    parity.check(phi, ref["phi"], (1e-10 if st.iters == ref["iters"] else 1e-7))
     phi2, st2, rc2 = h.source_iterate(o)
     assert rc2 == 0 and st2.iters == st.iters and np.array_equal(phi, phi2)

@@ -7,6 +7,9 @@ iterations from phi = 0 and compares the flux with the oracle's four iterations.
 import numpy as np
 import pytest
 
+import parity
+from parity import nrm
+
 pytestmark = pytest.mark.gpu
 
 CASES = 64
@@ -20,10 +23,6 @@ def R():
     from paper_2407_12527_amd import rom
     rom.lib()
     return rom
-
-
-def nrm(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
 def draw(R, orc, seed):
@@ -93,7 +92,7 @@ def test_random_configuration(R, orc, seed):
     ref = orc.source_iterate(p, c["d"], c["w"], W, scheme=orc.SCHEME_DD if c["dd"] else orc.SCHEME_STEP,
                              tol=0.0, max_iter=4)["phi"]
     summary = {k: c[k] for k in ("nx", "ny", "fp64", "dd", "scat", "norm", "kw")}
-    assert nrm(phi, ref) < c["tol"], (summary, len(c["w"]))
+    parity.check(phi, ref, c["tol"], what=str((summary, len(c["w"]))))
 
 
 @pytest.mark.parametrize("seed", range(24))
@@ -130,7 +129,7 @@ def test_random_ensemble(R, orc, seed):
         W = None if ok is None else orc.build_W(d, w, ok | orc.SCAT_NORMALIZE, 0.7, fold=1)
         ref = orc.source_iterate(p, d, w, W, scheme=orc.SCHEME_DD if dd else orc.SCHEME_STEP, tol=0.0,
                                  max_iter=4)["phi"]
-        assert nrm(phis[k], ref) < tol, (k, nx, ny, nz, nt, t, fp64, dd, scat)
+        parity.check(phis[k], ref, tol, what=str((k, nx, ny, nz, nt, t, fp64, dd, scat)))
 
 
 @pytest.mark.parametrize("seed", range(16))
@@ -161,7 +160,7 @@ def test_random_batch(R, orc, seed):
     assert rc == R.ROM_NOT_CONVERGED
     for i in range(k):
         assert stats[i].iters == 4
-        assert nrm(outs[i], refs[i]) < (1e-11 if fp64 else 1e-5), (i, k, fp64)
+        parity.check(outs[i], refs[i], (1e-11 if fp64 else 1e-5), what=str((i, k, fp64)))
 
 
 @pytest.mark.parametrize("seed", range(16))
@@ -193,4 +192,4 @@ def test_random_slab(R, orc, seed):
         if fp64:
             assert np.max(np.abs(phis[k] - ref)) <= 1e-12 * np.max(np.abs(ref)), (k, nx, n, kind, t)
         else:
-            assert nrm(phis[k], ref) < 1e-5, (k, nx, n, kind, t)
+            parity.check(phis[k], ref, 1e-5, what=str((k, nx, n, kind, t)))

@@ -6,6 +6,9 @@ FP64 oracle on the same bit-identical ordinate set, to the same bars as the othe
 import numpy as np
 import pytest
 
+import parity
+from parity import nrm
+
 import rom_inputs as RI
 
 pytestmark = pytest.mark.gpu
@@ -19,10 +22,6 @@ def R():
     from paper_2407_12527_amd import rom
     rom.lib()
     return rom
-
-
-def nrm(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
 def rand_problem(rng, nx, ny, ratio=0.9):
@@ -51,7 +50,7 @@ def test_new_ordinates_same_and_changed_layout(R, orc, prec):
         phi, stt, rc = h.source_iterate(o)
         ref = orc.source_iterate(p, d, w, None, tol=0.0, max_iter=7)
         assert rc == R.ROM_NOT_CONVERGED and stt.iters == 7
-        assert nrm(phi, ref["phi"]) < bar
+        parity.check(phi, ref["phi"], bar)
 
 
 def test_new_angular_inflow_values(R, orc):
@@ -69,12 +68,12 @@ def test_new_angular_inflow_values(R, orc):
         p = orc.Problem(nx, ny, st, ss, q, inflow_angular={"right": np.ascontiguousarray(ang)})
         phi, _, _ = h.source_iterate(o)
         ref = orc.source_iterate(p, d, w, None, tol=0.0, max_iter=5)
-        assert nrm(phi, ref["phi"]) < 1e-11, rep
+        parity.check(phi, ref["phi"], 1e-11, what=str(rep))
     # back to vacuum: the plan's inflow presence changes, so it is rebuilt
     h.set_inflow_angular(R.ROM_FACE_RIGHT, None)
     phi, _, _ = h.source_iterate(o)
     ref = orc.source_iterate(orc.Problem(nx, ny, st, ss, q), d, w, None, tol=0.0, max_iter=5)
-    assert nrm(phi, ref["phi"]) < 1e-11
+    parity.check(phi, ref["phi"], 1e-11)
 
 
 @pytest.mark.parametrize("prec", ["fp32", "fp64"])
@@ -92,7 +91,7 @@ def test_anisotropic_new_ordinates_and_g(R, orc, prec):
         W = orc.build_W(d, w, orc.SCAT_HG, g, fold=1)
         phi, _, _ = h.source_iterate(o)
         ref = orc.source_iterate(p, d, w, W, tol=0.0, max_iter=6)
-        assert nrm(phi, ref["phi"]) < (1e-11 if fp64 else 2e-3), (sample, g)
+        parity.check(phi, ref["phi"], (1e-11 if fp64 else 2e-3), what=str((sample, g)))
 
 
 def test_batch_repeat_and_changed_member(R, orc):
@@ -118,12 +117,12 @@ def test_batch_repeat_and_changed_member(R, orc):
     assert rc3 == 0
     for k in range(len(hs)):
         ref = orc.source_iterate(probs[k], sets[k][0], sets[k][1], None, tol=1e-6)["phi"]
-        assert nrm(out3[k], ref) < 1e-5, k
+        parity.check(out3[k], ref, 1e-5, what=str(k))
     # the same handles in another order form another batch
     out4, _, rc4 = R.solve_batch(hs[::-1], o)
     assert rc4 == 0
     for a, b in zip(out4[::-1], out3):
-        assert nrm(a, b) < 1e-6
+        parity.check(a, b, 1e-6)
 
 
 def test_ensemble_twice_other_seed(R, orc):
@@ -136,7 +135,8 @@ def test_ensemble_twice_other_seed(R, orc):
         mean, var, st, rc = h.ensemble(5, seed, R.ROM_ORD_STRATIFIED, 2, 4, o)
         ref = orc.ensemble(p, orc.ORD_STRATIFIED, 2, 4, seed, 5, tol=1e-7)
         assert rc == 0
-        assert nrm(mean, ref["mean"]) < 1e-10 and nrm(var, ref["var"]) < 1e-8, seed
+        parity.check(mean, ref["mean"], 1e-10, what=str(seed))
+        parity.check(var, ref["var"], 1e-8, what=str(seed))
 
 
 def test_autotuned_shape_reported(R):
@@ -196,7 +196,7 @@ def test_distinct_handles_from_several_threads(R, orc):
             t.join(timeout=120)
         assert not errs, (rnd, errs)
         for k in range(len(probs)):
-            assert nrm(out[k], refs[k]) < 1e-5, (rnd, k)
+            parity.check(out[k], refs[k], 1e-5, what=str((rnd, k)))
 
 
 def test_solve_on_a_caller_stream(R, orc):
@@ -226,4 +226,4 @@ def test_solve_on_a_caller_stream(R, orc):
     mean_b, _, _, rc_b = b.ensemble(6, 2, R.ROM_ORD_STRATIFIED, 2, 2, R.si_opts(tol=1e-6))
     assert rc_a == 0 and rc_b == 0 and np.array_equal(mean_a, mean_b)
     ref = orc.source_iterate(orc.Problem(nx, ny, st, ss, q), d, w, None, tol=1e-6)["phi"]
-    assert nrm(phi_b, ref) < 1e-5
+    parity.check(phi_b, ref, 1e-5)

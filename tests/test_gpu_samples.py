@@ -5,6 +5,9 @@ the ensemble moments, and the diamond-difference linear-kernel setting of the co
 import numpy as np
 import pytest
 
+import parity
+from parity import nrm
+
 import rom_inputs as RI
 
 pytestmark = pytest.mark.gpu
@@ -20,10 +23,6 @@ def R():
     return rom
 
 
-def nrm(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
-
-
 @pytest.mark.parametrize("first", [0, 5, 1000])
 def test_samples_match_oracle(R, orc, first):
     f = RI.uniform_fields(30, 26, 1.0, 0.6, 0.4, 0.6)
@@ -35,7 +34,7 @@ def test_samples_match_oracle(R, orc, first):
     for k in range(4):
         d, w = orc.generate(orc.ORD_STRATIFIED, 2, 3, seed=9, sample=first + k)
         ref = orc.source_iterate(p, d, w, None, tol=1e-13)["phi"]
-        assert nrm(phis[k], ref) < 1e-9, k
+        parity.check(phis[k], ref, 1e-9, what=str(k))
 
 
 @pytest.mark.parametrize("prec,scheme", [("fp32", "step"), ("fp64", "dd"), ("fp32", "dd")])
@@ -61,7 +60,7 @@ def test_samples_with_boundary_inflow(R, orc, prec, scheme):
         d, w = orc.generate(orc.ORD_STRATIFIED, 2, 2, seed=21, sample=k)
         osch = orc.SCHEME_DD if scheme == "dd" else orc.SCHEME_STEP
         ref = orc.source_iterate(p, d, w, None, tol=0.0, max_iter=6, scheme=osch)["phi"]
-        assert nrm(phis[k], ref) < (1e-12 if fp64 else 1e-5), k
+        parity.check(phis[k], ref, (1e-12 if fp64 else 1e-5), what=str(k))
 
 
 def test_samples_agree_with_moments_and_pieces(R):
@@ -91,7 +90,7 @@ def test_samples_dd_linear_kernel(R, orc):
         d, w = orc.generate(orc.ORD_STRATIFIED, 3, 3, seed=2024, sample=17 + k)
         W = orc.build_W(d, w, orc.SCAT_LINEAR, 0.9, fold=1)
         ref = orc.source_iterate(p, d, w, W, scheme=orc.SCHEME_DD, tol=1e-13)["phi"]
-        assert nrm(phis[k], ref) < 1e-9, k
+        parity.check(phis[k], ref, 1e-9, what=str(k))
 
 
 def test_samples_argument_errors(R):

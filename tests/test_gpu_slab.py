@@ -6,6 +6,9 @@ counts (1e-12 relative, max-norm) and FP32 to convergence (1e-5 normwise)."""
 import numpy as np
 import pytest
 
+import parity
+from parity import nrm
+
 import rom_inputs as RI
 
 pytestmark = pytest.mark.gpu
@@ -19,10 +22,6 @@ def R():
     from paper_2407_12527_amd import rom
     rom.lib()
     return rom
-
-
-def nrm(a, b):
-    return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / max(np.linalg.norm(b), 1e-300))
 
 
 def oracle_phi(orc, f, mu, w, tol, max_iter):
@@ -57,8 +56,8 @@ def test_converged_fp32_and_fp64(R, orc, case):
     assert rc == 0
     for k in (0, 41, 99):
         ref = oracle_phi(orc, f, mu[k], w[k], 1e-13, 10000)
-        assert nrm(p32[k], ref["phi"]) < 1e-5
-        assert nrm(p64[k], ref["phi"]) < 1e-11
+        parity.check(p32[k], ref["phi"], 1e-5)
+        parity.check(p64[k], ref["phi"], 1e-11)
         # same stopping rule, same tolerance: the same iteration (up to a rounding tie)
         assert abs(int(it64[k]) - oracle_phi(orc, f, mu[k], w[k], 1e-12, 10000)["iters"]) <= 1
 
