@@ -220,6 +220,22 @@ int rom_set_scattering(rom_handle* h, int32_t kind, double g, const double* P);
 int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double* phi, double* psi,
               const rom_si_opts* opts);
 
+/* For callers that cannot allocate device memory (work under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the sweep of rom_sweep for an isotropic source, on
+ * device arrays, taking no device memory.  src_dev and phi_dev are DEVICE pointers to [cells]
+ * floats (precision ROM_PREC_FP32) or doubles (ROM_PREC_FP64), src shared by all ordinates; phi
+ * receives sum_l w_l psi_l with the handle's ordinates and inflow (step scheme; rom_sweep's tile
+ * and band, hence its result bit for bit).  Every buffer the sweep needs lives in a 64 MiB region
+ * preallocated per GPU when the library is loaded and held until the process ends; a problem whose
+ * tables, partial fluxes and strip edges do not fit is refused with ROM_E_UNSUPPORTED.  The work
+ * is queued on hip_stream (NULL: the null stream) and the call returns without waiting for it.
+ * The first call for a handle state (ordinates, inflow) and precision fills the region from the
+ * host and waits for that upload; later calls for the same handle only launch kernels.  All
+ * calls on one GPU share its region: calls that overlap on one GPU (other streams, other
+ * threads while work is still queued) race.  A dependency wait that timed out is not reported
+ * (the call does not wait for the device). */
+int rom_sweep_noalloc(rom_handle* h, const void* src_dev, void* phi_dev, int32_t precision, void* hip_stream);
+
 /* Source iteration to convergence for the handle's ordinates and scattering kernel.  phi [cells]
  * receives the final scalar flux, or may be NULL to leave it on the device (see rom_phi_device).
  * Returns ROM_NOT_CONVERGED if max_iter was reached. */

@@ -60,13 +60,14 @@ struct DevMem {
     // even when the hook has been changed since
     void (*freefn)(void*, void*) = nullptr;
     void* fctx = nullptr;
+    bool view = false;  // a region of memory owned elsewhere (a plan placed in a caller's region)
     DevMem() = default;
     DevMem(const DevMem&) = delete;
     DevMem& operator=(const DevMem&) = delete;
     ~DevMem() { release(); }
     void release()
     {
-        if (p) {
+        if (p && !view) {
             if (freefn) {
                 // hipFree waits for the device; a hook gets the same guarantee: no queued work
                 // still uses the block when its allocator may hand it out again
@@ -80,6 +81,14 @@ struct DevMem {
         bytes = 0;
         freefn = nullptr;
         fctx = nullptr;
+        view = false;
+    }
+    void set_view(void* ptr, size_t n)
+    {
+        release();
+        p = ptr;
+        bytes = n;
+        view = true;
     }
     hipError_t alloc(size_t n)
     {
@@ -160,6 +169,7 @@ uint16_t f32_to_bf16(float f)
 
 // ------------------------------------------------------------------------------------ handle
 struct Plan;
+struct Arena;
 
 struct rom_handle {
     rom_grid grid{};
@@ -187,6 +197,12 @@ struct rom_handle {
     std::string plan_sig;
     // plans of the last ensemble and of the last batch led by this handle, kept for reuse
     std::unique_ptr<Plan> ens_plan, batch_plan;
+    // host side of the plan placed in the preallocated scratch region (rom_sweep_noalloc), for
+    // the handle's state `na_version` and precision `na_prec`
+    std::unique_ptr<Plan> na_plan;
+    std::unique_ptr<Arena> na_arena;
+    uint64_t na_version = 0;
+    int na_prec = -1;
     std::string ens_key, batch_key, batch_versions;
     uint64_t uid = next_uid();
     // autotuner choices of the batch shapes this handle led (key -> sweep, tile x, tile y, band,
@@ -232,7 +248,18 @@ struct SysInput {
     bool use_angular;  // angular inflow of the handle applies (its own ordinate set)
 };
 
+// A caller-provided device region that a plan's buffers are carved from instead of being
+// allocated: uploads are stream-ordered on `s` from host copies the plan keeps, and buffers that
+// must start at zero are cleared by a fill kernel (no hipMemset, so the work can be captured).
+struct Arena {
+    char* base = nullptr;
+    size_t cap = 0, used = 0;
+    hipStream_t s = nullptr;
+};
+
 struct Plan {
+    Arena* arena = nullptr;                 // placement of the buffers (NULL: allocated)
+    std::vector<std::vector<char>> keep;    // host sources of the arena uploads
     bool fp64 = false, dd = false, aniso = false;
     int nmom = 1;       // 4: linear-kernel moment sweep (three source planes, four partial planes)
     int mom_r = 0;      // linear kernel normalized somewhere in the batch: form phi~ separately
@@ -264,6 +291,7 @@ struct Plan {
     std::vector<float> h_inflow32;
     std::vector<double> h_bt64;
     std::vector<uint16_t> h_bt16;
+    int prog_count = 0;  // progress counters (64-bit words)
     int cells_per_block = 1024;
     int many_cpt = 0;  // many-slot combine: cells per thread (0: the few-slot combine)
     int vec = 0;       // many-slot combine with 16-byte loads
@@ -421,6 +449,48 @@ rom_handle::~rom_handle()
 }
 
 namespace {
+
+// ---- placement of a plan's device buffers (allocated, or carved from the plan's arena)
+void take(Plan& P, DevMem& d, size_t n)
+{
+    if (!P.arena) {
+        HIPCHK(d.alloc(n));
+        return;
+    }
+    if (n == 0) n = 256;
+    const size_t off = (P.arena->used + 255) & ~size_t(255);
+    if (off + n > P.arena->cap) {
+        char msg[160];
+        std::snprintf(msg, sizeof msg, "problem needs more than the %zu bytes of the preallocated scratch region",
+                      P.arena->cap);
+        throw Fail{ROM_E_UNSUPPORTED, msg};
+    }
+    d.set_view(P.arena->base + off, n);
+    P.arena->used = off + n;
+}
+
+template <typename T>
+void put(Plan& P, DevMem& d, const std::vector<T>& v)
+{
+    if (!P.arena) {
+        upload(d, v);
+        return;
+    }
+    const size_t bytes = v.size() * sizeof(T);
+    take(P, d, bytes);
+    if (bytes == 0) return;
+    P.keep.emplace_back((const char*)v.data(), (const char*)v.data() + bytes);
+    HIPCHK(hipMemcpyAsync(d.p, P.keep.back().data(), bytes, hipMemcpyHostToDevice, P.arena->s));
+}
+
+void zero(Plan& P, void* p, size_t bytes)
+{
+    if (!P.arena) {
+        HIPCHK(hipMemset(p, 0, bytes));
+        return;
+    }
+    HIPCHK(launch_fill(p, (int64_t)(bytes / 4), false, 0.0, P.arena->s));  // every cleared buffer is 4-byte sized
+}
 
 // The vector-load many-slot combine is the default; ROM_VEC_COMBINE=0 selects the scalar one.
 bool vec_combine_enabled()
@@ -986,28 +1056,31 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         for (int64_t c0 = 0; c0 < in[s].h->cells; c0 += P.cells_per_block) P.cblocks.push_back(make_int2(s, (int)c0));
 
     // ---- device buffers
-    upload(P.d_probs, P.probs);
-    upload(P.d_sys, P.sys);
-    upload(P.d_ws, P.ws);
-    upload(P.d_lanes, P.lanes);
-    upload(P.d_tickets, P.tickets);
-    upload(P.d_slot_off, P.slot_off);
-    upload(P.d_slot_order, P.slot_order);
+    put(P, P.d_probs, P.probs);
+    put(P, P.d_sys, P.sys);
+    put(P, P.d_ws, P.ws);
+    put(P, P.d_lanes, P.lanes);
+    put(P, P.d_tickets, P.tickets);
+    put(P, P.d_slot_off, P.slot_off);
+    put(P, P.d_slot_order, P.slot_order);
     P.slot_off_ord.resize(P.slot_order.size());
     for (size_t i = 0; i < P.slot_order.size(); ++i) P.slot_off_ord[i] = P.slot_off[P.slot_order[i]];
-    upload(P.d_slot_off_ord, P.slot_off_ord);
-    upload(P.d_cblocks, P.cblocks);
-    upload(P.d_uflags, uflags);
-    upload(P.d_dtasks, P.dtasks);
+    put(P, P.d_slot_off_ord, P.slot_off_ord);
+    put(P, P.d_cblocks, P.cblocks);
+    put(P, P.d_uflags, uflags);
+    put(P, P.d_dtasks, P.dtasks);
 
     auto cast_upload = [&](DevMem& d, const std::vector<double>& v) {
         if (P.fp64) {
-            upload(d, v);
+            put(P, d, v);
         } else {
             std::vector<float> f(v.begin(), v.end());
-            upload(d, f);
+            put(P, d, f);
         }
     };
+    // A single sweep placed in a caller's region takes its source and scalar flux from the
+    // caller and forms no next source: no sigma_s, q, source or flux pools of its own.
+    const bool caller_io = P.arena && max_iter == 0;
     std::vector<double> st(fsum), ss(fsum), qv(fsum);
     for (int p = 0; p < nprob; ++p) {
         rom_handle* h = P.handles[p];
@@ -1020,8 +1093,10 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         std::copy(st.begin(), st.end(), padded.begin() + kPoolPad);
         cast_upload(P.d_st, padded);
     }
-    cast_upload(P.d_ss, ss);
-    cast_upload(P.d_q, qv);
+    if (!caller_io) {
+        cast_upload(P.d_ss, ss);
+        cast_upload(P.d_q, qv);
+    }
 
     // inflow in sweep order, scaled by the lane weight
     P.inflow_len = inflow_sum;
@@ -1029,25 +1104,28 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         const std::vector<double> inf = P.kind == ROM_SWEEP_DIAG ? diag_inflow_table(P, in) : inflow_table(P, in);
         cast_upload(P.d_inflow, inf);
     } else {
-        HIPCHK(P.d_inflow.alloc(256));
+        take(P, P.d_inflow, 256);
     }
 
     P.src_len = src_sum;
-    HIPCHK(P.d_src.alloc((src_sum + 2 * kPoolPad) * P.esz));
-    HIPCHK(hipMemset(P.d_src.p, 0, (src_sum + 2 * kPoolPad) * P.esz));
-    HIPCHK(P.d_phi.alloc(phi_sum * P.esz));
-    HIPCHK(P.d_part.alloc(std::max<int64_t>(part_sum, 1) * P.esz));
-    HIPCHK(P.d_edge.alloc(std::max<int64_t>(edge_sum, 1) * P.esz));
-    HIPCHK(P.d_prog.alloc(std::max(prog_sum, 1) * sizeof(long long)));
-    HIPCHK(hipMemset(P.d_prog.p, 0, std::max(prog_sum, 1) * sizeof(long long)));
-    HIPCHK(P.d_ctl.alloc(sizeof(Ctl)));
-    HIPCHK(hipMemset(P.d_ctl.p, 0, sizeof(Ctl)));
-    HIPCHK(P.d_sysctl.alloc(P.nsys * sizeof(SysCtl)));
-    HIPCHK(hipMemset(P.d_sysctl.p, 0, P.nsys * sizeof(SysCtl)));
-    if (max_iter > 0) HIPCHK(P.d_rhist.alloc((size_t)P.nsys * max_iter * sizeof(double)));
+    if (!caller_io) {
+        take(P, P.d_src, (src_sum + 2 * kPoolPad) * P.esz);
+        zero(P, P.d_src.p, (src_sum + 2 * kPoolPad) * P.esz);
+        take(P, P.d_phi, phi_sum * P.esz);
+    }
+    take(P, P.d_part, std::max<int64_t>(part_sum, 1) * P.esz);
+    take(P, P.d_edge, std::max<int64_t>(edge_sum, 1) * P.esz);
+    P.prog_count = std::max(prog_sum, 1);
+    take(P, P.d_prog, P.prog_count * sizeof(long long));
+    zero(P, P.d_prog.p, P.prog_count * sizeof(long long));
+    take(P, P.d_ctl, sizeof(Ctl));
+    zero(P, P.d_ctl.p, sizeof(Ctl));
+    take(P, P.d_sysctl, P.nsys * sizeof(SysCtl));
+    zero(P, P.d_sysctl.p, P.nsys * sizeof(SysCtl));
+    if (max_iter > 0) take(P, P.d_rhist, (size_t)P.nsys * max_iter * sizeof(double));
     if (aniso) {
-        HIPCHK(P.d_ang.alloc(std::max<int64_t>(ang_sum, 1) * P.esz));
-        HIPCHK(P.d_psi.alloc(std::max<int64_t>(ang_sum, 1) * (P.fp64 ? 8 : 2)));
+        take(P, P.d_ang, std::max<int64_t>(ang_sum, 1) * P.esz);
+        take(P, P.d_psi, std::max<int64_t>(ang_sum, 1) * (P.fp64 ? 8 : 2));
     }
 }
 
@@ -1748,6 +1826,83 @@ int rom_sweep(rom_handle* h, const double* src, int32_t src_per_ordinate, double
 }
 
 }  // extern "C"
+
+// rom_sweep's work for a device-resident isotropic source, with every device buffer placed in a
+// preallocated region: the plan (tables, sigma_t pool, inflow, partial-flux slots, strip edges,
+// progress counters, control state) is built on the host once per handle state and precision and
+// uploaded into the region; `owner` (three words per device) records whose plan the region
+// holds, so repeated calls for the same handle only clear the counters and launch the sweep and
+// the combine, all on the caller's stream, without waiting for the device.
+int rom::sweep_in_scratch(rom_handle* h, void* scratch, size_t cap, uint64_t* owner, const void* src, void* phi,
+                          int32_t precision, void* stream)
+{
+    ROM_API_LOCK;
+    if (!h) return ROM_E_ARG;
+    if (!src || !phi) return fail(h, ROM_E_ARG, "src and phi must be device pointers");
+    if (!scratch || !owner) return fail(h, ROM_E_DEVICE, "scratch region unavailable");
+    if (h->n == 0) return fail(h, ROM_E_STATE, "set ordinates first");
+    if (precision != ROM_PREC_FP32 && precision != ROM_PREC_FP64) return fail(h, ROM_E_ARG, "bad precision");
+    const hipStream_t s = (hipStream_t)stream;
+    try {
+        const uint64_t state = (h->version << 1) | (uint64_t)precision;
+        const bool placed = h->na_plan && h->na_version == h->version && h->na_prec == precision &&
+                            owner[0] == h->uid && owner[1] == state && owner[2] == 1;
+        if (!placed) {
+            owner[2] = 0;  // the region's contents are being replaced
+            // the previous plan's host copies may still feed uploads queued on another stream
+            if (h->na_plan && h->na_plan->arena) HIPCHK(hipStreamSynchronize(h->na_plan->arena->s));
+            h->na_plan.reset();
+            rom_si_opts o;
+            std::memset(&o, 0, sizeof(o));
+            o.precision = precision;
+            o.sweep = ROM_SWEEP_STRIP;  // as rom_sweep
+            std::vector<SysInput> in{{h, h->dirs.data(), h->w.data(), h->n, true}};
+            std::unique_ptr<Plan> P(new Plan());
+            std::unique_ptr<Arena> ar(new Arena{(char*)scratch, cap, 0, s});
+            P->arena = ar.get();
+            try {
+                build_plan(*P, in, o, 0, 0, false);
+            } catch (...) {
+                (void)hipStreamSynchronize(s);  // uploads already queued read the plan's host copies
+                throw;
+            }
+            HIPCHK(hipStreamSynchronize(s));  // tables in place before their host copies can go
+            P->keep.clear();
+            P->keep.shrink_to_fit();
+            h->na_arena.reset(ar.release());
+            h->na_plan.reset(P.release());
+            h->na_version = h->version;
+            h->na_prec = precision;
+            owner[0] = h->uid;
+            owner[1] = state;
+            owner[2] = 1;
+        }
+        Plan& P = *h->na_plan;
+        h->na_arena->s = s;
+        // counters that must start at zero, then a fresh control state (ticket 0, epoch 1)
+        HIPCHK(launch_fill(P.d_prog.p, (int64_t)P.prog_count * 2, false, 0.0, s));
+        HIPCHK(launch_fill(P.d_ctl.p, (int64_t)(sizeof(Ctl) / 4), false, 0.0, s));
+        HIPCHK(launch_reset_systems(P.d_sysctl.as<SysCtl>(), 1, P.d_ctl.as<Ctl>(), s));
+        SweepArgs sa = P.sweep_args(1, 0);
+        sa.src = src;
+        HIPCHK(launch_sweep(sa, P.grid, P.fp64, P.tx, P.ty, P.dd, false, 0, P.L, 1, s));
+        CombineArgs ca = P.combine_args(1, 0.0);
+        ca.phi = phi;
+        ca.src = nullptr;
+        ca.sigma_s = nullptr;
+        ca.q = nullptr;
+        HIPCHK(launch_combine(ca, (int)P.cblocks.size(), P.fp64, s));
+    } catch (const Fail& f) {
+        owner[2] = 0;
+        h->na_plan.reset();
+        return fail(h, f.code, f.msg);
+    } catch (const std::bad_alloc&) {
+        owner[2] = 0;
+        h->na_plan.reset();
+        return fail(h, ROM_E_NOMEM, "host allocation failed");
+    }
+    return ROM_OK;
+}
 
 namespace {
 

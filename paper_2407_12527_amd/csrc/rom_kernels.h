@@ -68,7 +68,8 @@ struct CombineArgs {
     int32_t nsys;
     int32_t nmom;              // partial planes per slot: 1 (phi) or 4 (linear kernel: phi, Jx~,
                                // Jy~, phi~); sources: 1 or 3 planes
-    int32_t mode;              // 0: source-iteration step, 1: plain sum (single sweep)
+    int32_t mode;              // 0: source-iteration step, 1: plain sum (single sweep: phi only;
+                               // src, sigma_s and q are not touched and may be NULL)
     int32_t max_iter;
     int32_t mom_r;             // linear kernel: phi~ comes from plane 3 (else phi~ = phi)
     int32_t vec;               // 16-byte loads (every system's cell count a multiple of 16 B /

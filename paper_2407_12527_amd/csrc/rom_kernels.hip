@@ -145,7 +145,7 @@ __global__ __launch_bounds__(256) void combine_kernel(CombineArgs A)
                     dmax = fmax(dmax, fabs((double)v[u] - (double)old[u]));
                     pmax = fmax(pmax, fabs((double)v[u]));
                     phi[cell] = v[u];
-                    src[cell] = fma(ss[cell], v[u], q[cell]);
+                    if (A.mode == 0) src[cell] = fma(ss[cell], v[u], q[cell]);
                 }
             }
         }
@@ -214,7 +214,7 @@ __global__ __launch_bounds__(256) void combine_many_kernel(CombineArgs A)
                 dmax = fmax(dmax, fabs((double)v - (double)old));
                 pmax = fmax(pmax, fabs((double)v));
                 phi[cell] = v;
-                src[cell] = fma(ss[cell], v, q[cell]);
+                if (A.mode == 0) src[cell] = fma(ss[cell], v, q[cell]);
             }
         }
     }
@@ -266,8 +266,10 @@ __global__ __launch_bounds__(64 * NW) void combine_vec_kernel(CombineArgs A)
     T old = T(0), ssv = T(0), qv = T(0);
     if (upd) {
         old = phi[ucell];
-        ssv = ((const T*)A.sigma_s + P.field_off)[ucell];
-        qv = ((const T*)A.q + P.field_off)[ucell];
+        if (A.mode == 0) {
+            ssv = ((const T*)A.sigma_s + P.field_off)[ucell];
+            qv = ((const T*)A.q + P.field_off)[ucell];
+        }
     }
     if (run) {
         const T* __restrict__ part = (const T*)A.part;
@@ -303,7 +305,7 @@ __global__ __launch_bounds__(64 * NW) void combine_vec_kernel(CombineArgs A)
         dmax = fabs((double)v - (double)old);
         pmax = fabs((double)v);
         phi[ucell] = v;
-        src[ucell] = fma(ssv, v, qv);
+        if (A.mode == 0) src[ucell] = fma(ssv, v, qv);
     }
     combine_tail(A, run, s, dmax, pmax);
 }
@@ -350,8 +352,8 @@ __global__ __launch_bounds__(256) void combine_vec_few_kernel(CombineArgs A)
 #pragma unroll
             for (int k = 0; k < 8; ++k) acc[t][k] = (in && k < ns) ? *(const V4*)(sp[k] + c0) : V4{};
             old[t] = in ? *(const V4*)(phi + c0) : V4{};
-            ssv[t] = in ? *(const V4*)(ssp + c0) : V4{};
-            qv[t] = in ? *(const V4*)(qp + c0) : V4{};
+            ssv[t] = (in && A.mode == 0) ? *(const V4*)(ssp + c0) : V4{};
+            qv[t] = (in && A.mode == 0) ? *(const V4*)(qp + c0) : V4{};
         }
 #pragma unroll
         for (int t = 0; t < TPB; ++t) {
@@ -372,7 +374,7 @@ __global__ __launch_bounds__(256) void combine_vec_few_kernel(CombineArgs A)
                 snv[i] = fma(sv[i], tv[i], qq[i]);
             }
             *(V4*)(phi + c0) = tot;
-            *(V4*)(src + c0) = sn;
+            if (A.mode == 0) *(V4*)(src + c0) = sn;
         }
     }
     combine_tail(A, run, s, dmax, pmax);

@@ -25,7 +25,7 @@ __all__ = [
     "ROM_FACE_TOP", "rom_grid", "rom_inflow", "rom_ord_spec", "rom_si_opts", "rom_si_stats", "rom_ens_stats",
     "RomError", "Handle", "lib", "library_path", "EXPORTS", "generate_ordinates", "ordinate_count",
     "solve_batch", "si_opts", "rom_create", "rom_destroy", "rom_set_stream", "rom_set_ordinates",
-    "rom_set_inflow_angular", "rom_set_scattering", "rom_sweep", "rom_source_iterate", "rom_ensemble",
+    "rom_set_inflow_angular", "rom_set_scattering", "rom_sweep", "rom_sweep_noalloc", "rom_source_iterate", "rom_ensemble",
     "rom_ensemble_samples", "rom_solve_batch", "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
     "rom_last_error", "rom_version", "rom_slab_create", "rom_slab_destroy", "rom_slab_set_stream", "rom_slab_solve",
     "rom_slab_ordinates", "rom_slab_last_error", "ROM_SLAB_RANDOM", "ROM_SLAB_GAUSS", "ROM_SLAB_UNIFORM", "Slab",
@@ -46,7 +46,7 @@ ROM_SLAB_RANDOM, ROM_SLAB_GAUSS, ROM_SLAB_UNIFORM = 0, 1, 2
 
 # every function declared in include/rom.h
 EXPORTS = ("rom_create", "rom_destroy", "rom_set_stream", "rom_set_allocator", "rom_set_ordinates", "rom_set_inflow_angular",
-           "rom_set_scattering", "rom_sweep", "rom_source_iterate", "rom_ensemble", "rom_ensemble_samples",
+           "rom_set_scattering", "rom_sweep", "rom_sweep_noalloc", "rom_source_iterate", "rom_ensemble", "rom_ensemble_samples",
            "rom_solve_batch",
            "rom_phi_device", "rom_generate_ordinates", "rom_ordinate_count", "rom_status_string",
            "rom_last_error", "rom_version", "rom_slab_create", "rom_slab_destroy", "rom_slab_set_stream",
@@ -121,6 +121,7 @@ def lib():
         L.rom_set_inflow_angular.argtypes = [P, C.c_int32, P]
         L.rom_set_scattering.argtypes = [P, C.c_int32, C.c_double, P]
         L.rom_sweep.argtypes = [P, P, C.c_int32, P, P, C.POINTER(rom_si_opts)]
+        L.rom_sweep_noalloc.argtypes = [P, P, P, C.c_int32, P]
         L.rom_source_iterate.argtypes = [P, C.POINTER(rom_si_opts), P, C.POINTER(rom_si_stats)]
         L.rom_ensemble.argtypes = [P, C.c_int32, C.c_uint64, C.POINTER(rom_ord_spec), C.POINTER(rom_si_opts), P, P,
                                    C.POINTER(rom_ens_stats)]
@@ -181,6 +182,10 @@ def rom_set_scattering(h, kind, g, P):
 
 def rom_sweep(h, src, src_per_ordinate, phi, psi, opts):
     return lib().rom_sweep(h, src, src_per_ordinate, phi, psi, opts)
+
+
+def rom_sweep_noalloc(h, src_dev, phi_dev, precision, stream):
+    return lib().rom_sweep_noalloc(h, src_dev, phi_dev, precision, stream)
 
 
 def rom_source_iterate(h, opts, phi, stats):
