@@ -69,7 +69,9 @@ def parse():
     ap.add_argument("--repeats", type=int, default=3)
     ap.add_argument("--tol", type=float, default=1e-6, help="source-iteration tolerance of both arms")
     ap.add_argument("--out", default="", help="also append every JSON line to this file")
-    return ap.parse_args()
+    a = ap.parse_args()
+    a.quiet = False
+    return a
 
 
 def l2_err(phi, ref):
@@ -96,7 +98,8 @@ class Runner:
     def emit(self, rec):
         rec = {"problem": self.a.problem, **rec}
         line = json.dumps(rec)
-        print(line, flush=True)
+        if not getattr(self.a, "quiet", False):
+            print(line, flush=True)
         if self.outf:
             self.outf.write(line + "\n")
             self.outf.flush()
@@ -162,6 +165,22 @@ def main():
     import torch
     from paper_2407_12527_amd import rom as R
     torch.cuda.set_device(0)
+    measure(a, R, torch)
+
+
+def options(**kw):
+    """The command-line defaults as an argparse namespace, overridden by `kw` (for callers that
+    import this module, such as bench.py)."""
+    ns = argparse.Namespace(problem="iso64", ref_n=0, dom_n="2-22", rom_n="16,36,64", t_max=4096, seeds=5,
+                            repeats=3, tol=1e-6, out="", quiet=False)
+    for k, v in kw.items():
+        setattr(ns, k, v)
+    return ns
+
+
+def measure(a, R, torch):
+    """Run the whole protocol for a.problem; emits one JSON line per measurement (unless
+    a.quiet) and returns the summary record."""
     run = Runner(a, R, torch)
     p = run.p
     ref_n = a.ref_n or p["ref_n"]
@@ -239,6 +258,7 @@ def main():
                "rom": {str(k): v for k, v in rom_summary.items()},
                "diverged": diverged, "wall_seconds": time.perf_counter() - t_start}
     run.emit(summary)
+    return summary
 
 
 if __name__ == "__main__":
