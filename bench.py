@@ -62,7 +62,7 @@ PINNED = {
     "c1": {"sweep": "diag", "diag_rows": 64, "diag_k": 1, "band": 2, "tile": "0x0"},
     "c2": {"sweep": "diag", "diag_rows": 64, "diag_k": 2, "band": 4, "tile": "0x0"},
     "c3": {"sweep": "strip", "tile": "16x16", "band": 4, "diag_rows": 0, "diag_k": 0},
-    "c4": {"sweep": "strip", "tile": "8x4", "band": 4, "diag_rows": 0, "diag_k": 0},
+    "c4": {"sweep": "diag", "diag_rows": 16, "diag_k": 4, "band": 4, "tile": "0x0"},
     "c5": {"sweep": "strip", "tile": "16x16", "band": 4, "diag_rows": 0, "diag_k": 0},
 }
 
@@ -71,7 +71,8 @@ PINNED = {
 # each workload.  Reported only while the kernel sources hash to what was profiled and the run
 # used that shape; otherwise `traffic` is null.
 KERNEL_SOURCES = {
-    "row-lane": ["rom_common.h", "rom_device.h", "rom_diag.h", "rom_diag_f32.hip", "rom_diag_f64.hip"],
+    "row-lane": ["rom_common.h", "rom_device.h", "rom_diag.h", "rom_diag_f32.hip", "rom_diag_f32_ang.hip",
+                 "rom_diag_f64.hip"],
     "strip": ["rom_common.h", "rom_device.h", "rom_sweep.h", "rom_sweep_f32_16x16.hip", "rom_sweep_f32_16x8.hip",
               "rom_sweep_f32_8x4.hip", "rom_sweep_f32_8x8.hip", "rom_sweep_f64.hip"],
 }

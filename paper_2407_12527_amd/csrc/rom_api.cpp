@@ -165,6 +165,33 @@ uint16_t f32_to_bf16(float f)
     return uint16_t(u >> 16);
 }
 
+// Frequency of the device real-time clock read by wall_clock64(), in kHz (ticks per ms).
+double wallclock_khz()
+{
+    // initialized once per process, thread-safe (function-local static)
+    static const double khz = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
+            return (double)v;
+        return 100000.0;
+    }();
+    return khz;
+}
+
+// Real-time clock ticks a sweep's dependency wait may last before it gives up: 2 s.  A wait in a
+// working sweep lasts microseconds; a timed-out one ends the solve with ROM_E_DEVICE.
+long long wait_ticks() { return (long long)(2000.0 * wallclock_khz()); }
+
+// Polls a dependency wait may make before it gives up: 2^24, or ROM_SPIN_LIMIT (read when a plan's
+// launches are set up; tests force the time-out path with a tiny limit, and every kernel still
+// exits normally).
+int spin_limit()
+{
+    const char* e = std::getenv("ROM_SPIN_LIMIT");
+    const long v = e ? std::strtol(e, nullptr, 10) : 0;
+    return (v > 0 && v < (1L << 30)) ? (int)v : 1 << 24;
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------------------------ handle
@@ -342,7 +369,8 @@ struct Plan {
         a.sys = d_sys.as<SystemDev>();
         a.tickets = d_tickets.as<int2>();
         a.ntickets = ntickets;
-        a.spin_limit = 1 << 24;
+        a.spin_limit = spin_limit();
+        a.wait_ticks = wait_ticks();
         a.mode_all = mode_all;
         a.edge = d_edge.p;
         a.prog = d_prog.as<long long>();
@@ -353,13 +381,15 @@ struct Plan {
         a.inflow = d_inflow.p;
         a.ctl = d_ctl.as<Ctl>();
         a.sysctl = d_sysctl.as<SysCtl>();
+        a.ang_src = d_ang.p;
+        a.psi_out = d_psi.p;
         return a;
     }
 
     // one sweep of every running system, with the plan's kernel
     hipError_t launch_sweep_any(int mode_all, hipStream_t s) const
     {
-        if (kind == ROM_SWEEP_DIAG) return launch_diag(diag_args(mode_all), grid, dNB, fp64, dR, dK, s);
+        if (kind == ROM_SWEEP_DIAG) return launch_diag(diag_args(mode_all), grid, dNB, fp64, dR, dK, aniso, s);
         return launch_sweep(sweep_args(mode_all, 0), grid, fp64, tx, ty, dd, aniso, aniso ? (fp64 ? 1 : 2) : 0, L, nmom, s);
     }
 
@@ -372,7 +402,8 @@ struct Plan {
         a.sys = d_sys.as<SystemDev>();
         a.tickets = d_tickets.as<int2>();
         a.ntickets = ntickets;
-        a.spin_limit = 1 << 24;
+        a.spin_limit = spin_limit();
+        a.wait_ticks = wait_ticks();
         a.mode_all = mode_all;
         a.band = band;
         a.sigma_t = st_ptr();
@@ -510,19 +541,6 @@ int device_cus()
         return v;
     }();
     return cus;
-}
-
-// Frequency of the device real-time clock read by wall_clock64(), in kHz (ticks per ms).
-double wallclock_khz()
-{
-    // initialized once per process, thread-safe (function-local static)
-    static const double khz = [] {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) == hipSuccess && hipDeviceGetAttribute(&v, hipDeviceAttributeWallClockRate, dev) == hipSuccess && v > 0)
-            return (double)v;
-        return 100000.0;
-    }();
-    return khz;
 }
 
 void choose_tiles(const rom_si_opts& o, const std::vector<SysInput>& in, bool fp64, int& tx, int& ty)
@@ -719,8 +737,10 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     P.max_iter = max_iter;
     P.kind = o.sweep == ROM_SWEEP_DIAG ? ROM_SWEEP_DIAG : ROM_SWEEP_STRIP;
     if (P.kind == ROM_SWEEP_DIAG) {
-        if (aniso || psi_out || P.dd || P.nmom != 1)
-            throw Fail{ROM_E_UNSUPPORTED, "the row-lane sweep takes isotropic sources, the step scheme and no angular-flux output"};
+        if (psi_out || P.dd || P.nmom != 1 || (aniso && (P.fp64 || max_iter == 0)))
+            throw Fail{ROM_E_UNSUPPORTED,
+                       "the row-lane sweep takes the step scheme, isotropic sources or (FP32 source iteration) a dense "
+                       "kernel's per-ordinate sources, and no angular-flux output"};
         P.dR = o.diag_rows > 0 ? o.diag_rows : 16;
         P.dK = o.diag_k > 0 ? o.diag_k : 1;
         if (!diag_supported(P.fp64, P.dR, P.dK)) throw Fail{ROM_E_ARG, "unsupported row-lane sweep shape"};
@@ -867,7 +887,7 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         const int R = P.dR, K = P.dK, NO = (kWave / R) * K;
         int maxblocks = 1;
         for (auto& pd : P.probs) maxblocks = std::max(maxblocks, (pd.ny + R - 1) / R);
-        const int nbmax = diag_max_nb(P.fp64, K);
+        const int nbmax = diag_max_nb(P.fp64, K, aniso);
         int ntask = 0;
         for (int sy = 0; sy < P.nsys; ++sy)
             for (int q = 0; q < 4; ++q) ntask += ((int)ql[sy].idx[q].size() + NO - 1) / NO;
@@ -924,6 +944,16 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
                 }
             }
             P.npad_al[sy] = P.sys[sy].npad = (int)uo.size();
+        }
+        if (aniso) {
+            // the dense-kernel layout [cells][npad] in the row-lane order, padded for the GEMM tiles
+            ang_sum = 0;
+            for (int sy = 0; sy < P.nsys; ++sy) {
+                const int al = ((int)P.user_of[sy].size() + 127) / 128 * 128;
+                P.npad_al[sy] = P.sys[sy].npad = al;
+                P.sys[sy].ang_off = ang_sum;
+                ang_sum += P.handles[P.sys[sy].prob]->cells * (int64_t)al;
+            }
         }
     }
     std::vector<std::vector<double>> inv_r(P.nsys);
@@ -1252,6 +1282,7 @@ bool refresh_ordinates(Plan& P, const std::vector<SysInput>& in, hipStream_t s)
                 rewrite(P.d_inflow, P.h_inflow32, s);
             }
         }
+        if (P.aniso) build_kernel_matrices(P, in, s);
         return true;
     }
     // internal order: quadrant-major, L-lane groups, padded (as built)
@@ -1317,6 +1348,8 @@ ContractArgs contract_args(const Plan& P, int k)
     c.N = c.K = P.npad_al[k];
     c.sys_index = k;
     c.sysctl = P.d_sysctl.as<SysCtl>();
+    // the row-lane sweep keeps per-ordinate sources and angular fluxes in ordinate blocks of 16
+    c.blocked = (P.kind == ROM_SWEEP_DIAG && !P.fp64) ? 1 : 0;
     return c;
 }
 
@@ -1983,7 +2016,8 @@ void autotune(rom_handle* owner, std::vector<SysInput>& in, rom_si_opts& o, int 
         for (auto t : tiles)
             for (int band : {2, 4, 8}) cands.push_back({ROM_SWEEP_STRIP, t.first, t.second, band, 0, 0});
     }
-    if (o.sweep != ROM_SWEEP_STRIP && smode == 0 && o.scheme == ROM_SCHEME_STEP) {
+    // the row-lane kernel: isotropic step sweeps, and FP32 step sweeps of dense kernels
+    if (o.sweep != ROM_SWEEP_STRIP && o.scheme == ROM_SCHEME_STEP && (smode == 0 || (smode == 2 && !fp64))) {
         for (int rows : {16, 64})
             for (int k : {1, 2, 4})
                 if (diag_supported(fp64, rows, k) && (o.diag_rows == 0 || o.diag_rows == rows) && (o.diag_k == 0 || o.diag_k == k))

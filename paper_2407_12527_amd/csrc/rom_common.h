@@ -33,38 +33,52 @@ __device__ __forceinline__ T edge_load(const T* p) { return __hip_atomic_load(p,
 
 __device__ __forceinline__ void stores_complete() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
 
-// Wait until *p >= target (the strip below has finished chunk c of this epoch).  Bounded: after
-// `limit` polls (or once another wave has timed out) the wait gives up and records the error, so
-// every wave always exits.
-__device__ __forceinline__ void wait_progress(long long* p, long long target, Ctl* ctl, int limit)
+// Bounded waits.  A wait gives up and records ctl->error after `limit` polls or after `ticks`
+// ticks of the device real-time clock (wall_clock64), whichever comes first, and leaves early
+// without recording anything once another wave has recorded an error (checked every 64 polls).
+// The clock bound keeps a timed-out wait short however long a contended device-scope poll takes
+// (a poll count alone bounds it only by polls x poll latency), so every wave exits and the host
+// reports ROM_E_DEVICE.  Returns true when the wait gave up.
+__device__ __forceinline__ bool wait_gave_up(int spins, unsigned long long t0, Ctl* ctl, int limit, long long ticks)
 {
-    int spins = 0;
-    while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins >= limit) {
+    if (spins >= limit) {
+        __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        return true;
+    }
+    if ((spins & 63) == 0) {
+        if (__hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) return true;
+        if ((long long)(wall_clock64() - t0) > ticks) {
             __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
+            return true;
         }
-        if ((spins & 1023) == 0 &&
-            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-            break;
+    }
+    return false;
+}
+
+// Wait until *p >= target (the strip below has finished chunk c of this epoch).
+__device__ __forceinline__ void wait_progress(long long* p, long long target, Ctl* ctl, int limit, long long ticks)
+{
+    if (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+        const unsigned long long t0 = wall_clock64();
+        int spins = 0;
+        while (__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (wait_gave_up(++spins, t0, ctl, limit, ticks)) break;
+        }
     }
     asm volatile("" ::: "memory");  // edge loads stay after the poll
 }
 
 // Wait until an LDS counter of the workgroup reaches `target` (bounded like wait_progress).
-__device__ __forceinline__ void lds_wait(int* p, int target, Ctl* ctl, int limit)
+__device__ __forceinline__ void lds_wait(int* p, int target, Ctl* ctl, int limit, long long ticks)
 {
-    int spins = 0;
-    while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins >= limit) {
-            __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            break;
+    if (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+        const unsigned long long t0 = wall_clock64();
+        int spins = 0;
+        while (__hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (wait_gave_up(++spins, t0, ctl, limit, ticks)) break;
         }
-        if ((spins & 1023) == 0 &&
-            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-            break;
     }
 }
 

@@ -23,6 +23,14 @@
 // The field and source pools carry kPoolPad elements of padding on both sides, so the skewed
 // loads of lanes before or past their row need no clamping.
 //
+// Dense scattering kernels (ANG): the source is per (cell, ordinate), stored in ordinate blocks
+// of 16, S[npad / 16][cells][16], as the contraction writes it for this kernel.  The four slots
+// of a row hold 4K consecutive ordinates of one block, so at each step they read 16K contiguous
+// bytes of one cell (K floats per lane, the cell clamped into the grid for lanes outside their
+// row), and a lane's consecutive steps read consecutive cells of its block: each row of the block
+// is one stream through memory, not a stride of the whole ordinate set per cell.  The weighted
+// angular flux w psi of the cell goes back in the same layout as BF16, the contraction's input.
+//
 // Cell update (step scheme, unscaled psi, cells in sweep order):
 //   psi = (S + a psi_x + b psi_y) / (sigma_t + a + b),   a = |c|/dx, b = |s|/dy
 // and the task's partial scalar flux sum_k w_k psi_k is reduced over the 64 / R ordinate slots
@@ -41,8 +49,10 @@ constexpr int diag_ring() { return R == 16 ? 64 : 128; }
 // FP32 blocks are 16 steps long where the lane state still fits the VGPR budget (at most two
 // ordinates per lane and two prefetch sets, i.e. at most 8 waves per workgroup, 256 VGPRs);
 // otherwise 8.  FP64: 4.  (diag_pitch pads the y-face tables for 16.)
-template <typename T, int K, int PD>
-constexpr int diag_unroll() { return sizeof(T) == 8 ? 4 : (K <= 2 && PD == 2 ? 16 : 8); }
+// Dense-kernel variants hold K source values per step in their prefetch sets: 8 steps, 4 with
+// two or four ordinates per lane.
+template <typename T, int K, int PD, bool ANG = false>
+constexpr int diag_unroll() { return sizeof(T) == 8 ? 4 : ANG ? (K >= 2 ? 4 : 8) : (K <= 2 && PD == 2 ? 16 : 8); }
 // Most wavefronts per workgroup: 16, or 8 where the lane state needs more than 128 VGPRs (more
 // than one ordinate per lane, or loads kept PD = 2 blocks ahead).
 template <typename T, int K, int PD>
@@ -113,22 +123,20 @@ __device__ __forceinline__ void lds_publish(int* p, int v)
 }
 
 // Bounded wait on an LDS counter; returns the value seen (cached by the caller).  Reads that
-// follow stay after the poll (compiler barrier; LDS answers a wave's reads in order).
-__device__ __forceinline__ int lds_wait_get(int* p, int target, Ctl* ctl, int limit)
+// follow stay after the poll (compiler barrier; LDS answers a wave's reads in order).  Bounds as
+// wait_gave_up states; a wait that gave up returns the target.
+__device__ __forceinline__ int lds_wait_get(int* p, int target, Ctl* ctl, int limit, long long ticks)
 {
-    int spins = 0;
-    int v;
-    while ((v = *(volatile int*)p) < target) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins >= limit) {
-            __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            v = target;
-            break;
-        }
-        if ((spins & 1023) == 0 &&
-            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0) {
-            v = target;
-            break;
+    int v = *(volatile int*)p;
+    if (v < target) {
+        const unsigned long long t0 = wall_clock64();
+        int spins = 0;
+        while ((v = *(volatile int*)p) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (wait_gave_up(++spins, t0, ctl, limit, ticks)) {
+                v = target;
+                break;
+            }
         }
     }
     asm volatile("" ::: "memory");
@@ -137,19 +145,16 @@ __device__ __forceinline__ int lds_wait_get(int* p, int target, Ctl* ctl, int li
 
 // Bounded wait on a device-scope progress counter (another workgroup's band); returns the value
 // seen.  The counter carries the sweep's epoch in its high bits.
-__device__ __forceinline__ long long wait_progress_get(long long* p, long long target, Ctl* ctl, int limit)
+__device__ __forceinline__ long long wait_progress_get(long long* p, long long target, Ctl* ctl, int limit, long long ticks)
 {
-    int spins = 0;
-    long long v;
-    while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
-        __builtin_amdgcn_s_sleep(1);
-        if (++spins >= limit) {
-            __hip_atomic_store(&ctl->error, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            return target;
+    long long v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (v < target) {
+        const unsigned long long t0 = wall_clock64();
+        int spins = 0;
+        while ((v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) < target) {
+            __builtin_amdgcn_s_sleep(1);
+            if (wait_gave_up(++spins, t0, ctl, limit, ticks)) return target;
         }
-        if ((spins & 1023) == 0 &&
-            __hip_atomic_load(&ctl->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0)
-            return target;
     }
     asm volatile("" ::: "memory");  // edge loads stay after the poll
     return v;
@@ -170,7 +175,18 @@ struct DiagTask {
     T* edge_out;         // this band's top row for the band above, and its progress counter
     long long* prog_out;
     long long tag;       // sweep epoch << 24
+    const float* ang;    // dense kernels: per-ordinate source of the system [npad / 16][cells][16],
+    uint16_t* psi;       // its weighted angular flux (BF16 bits) in the same layout
+    int64_t cells;
+    int ord0;            // the task's first ordinate
 };
+
+// BF16 bits of x, rounded to nearest even (x finite)
+__device__ __forceinline__ uint32_t bf16_bits(float x)
+{
+    const uint32_t u = __float_as_uint(x);
+    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+}
 
 // U consecutive values at p (16-byte aligned) as 16-byte LDS or global accesses.
 template <typename T, int U>
@@ -290,14 +306,14 @@ enum { kInRing = 0, kInBoundary = 1, kInEdge = 2 };
 // top row of column c leaves the lane of row R - 1 at step c + R - 1; block t0 exports columns
 // t0 - R .. t0 - R + U - 1 (the previous block's last value and this block's first U - 1), so
 // every run is U-aligned.
-template <typename T, int R, int K, int PD, bool XPOS, int IN, int OUT>
+template <typename T, int R, int K, int PD, bool XPOS, int IN, int OUT, bool ANG>
 __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>& D, const int rb, const int wave,
                                            T* ring, int* prod, int* cons,
                                            const T (&a)[K], const T (&b)[K], const T (&ab)[K], const T (&w)[K])
 {
     constexpr int NG = kWave / R;
     constexpr int NO = NG * K;
-    constexpr int U = diag_unroll<T, K, PD>();
+    constexpr int U = diag_unroll<T, K, PD, ANG>();
     constexpr int RING = diag_ring<R>();
     constexpr int DIR = XPOS ? 1 : -1;  // storage step per sweep column
     static_assert(RING % U == 0 && R % U == 0, "runs must stay aligned");
@@ -328,19 +344,38 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
     // cells of steps t0 .. t0 + U - 1; lanes before or past their row read padding or a
     // neighbouring row, values that never reach a stored or exported result.  PD register sets
     // keep the loads PD blocks ahead of their use.
-    T pst[PD][U], pS[PD][U];
-    auto fetch = [&](T (&fst)[U], T (&fS)[U], int t0) {
+    constexpr int UA = ANG ? U : 1;
+    constexpr int KA = ANG ? K : 1;
+    typedef float VK __attribute__((ext_vector_type(KA)));
+    T pst[PD][U], pS[PD][ANG ? 1 : U];
+    VK pA[PD][UA];
+    // storage cell of step t, clamped into the lane's row (dense-kernel loads)
+    const int64_t rowbase = (int64_t)j * nx;
+    // the lane's K ordinates within their block of 16: element (cell, o) at ((o / 16) * cells + cell) * 16 + o % 16
+    const int ol = D.ord0 + g * K;
+    const int64_t obase = ANG ? ((int64_t)(ol / 16) * D.cells) * 16 + ol % 16 : 0;
+    const float* const ang_lane = ANG ? D.ang + obase : nullptr;
+    auto fetch = [&](T (&fst)[U], T (&fS)[ANG ? 1 : U], VK (&fA)[UA], int t0) {
         const int64_t c0 = lane0 + (int64_t)DIR * t0;
         load_row_run<T, U, DIR>(D.st, c0, fst);
-        load_row_run<T, U, DIR>(D.S, c0, fS);
+        if constexpr (ANG) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int c = min(max(t0 + u - r, 0), nx - 1);
+                const int64_t cell = rowbase + (XPOS ? c : nx - 1 - c);
+                fA[u] = *reinterpret_cast<const VK*>(ang_lane + cell * 16);
+            }
+        } else {
+            load_row_run<T, U, DIR>(D.S, c0, fS);
+        }
     };
     const int tsteps = nx + R - 1;                          // steps with a cell in the block
     const int tend = R + U * ((nx + U - 1) / U);            // ... and until the last column is exported
 #pragma unroll
     for (int q = 0; q < PD; ++q)
-        if (q * U < tsteps) fetch(pst[q], pS[q], q * U);
+        if (q * U < tsteps) fetch(pst[q], pS[q], pA[q], q * U);
 
-    auto block = [&](const int t0, const T (&cst)[U], const T (&cS)[U]) {
+    auto block = [&](const int t0, const T (&cst)[U], const T (&cS)[ANG ? 1 : U], const VK (&cA)[UA]) {
         // y-face inflow of row 0 for columns t0 .. t0 + U - 1 (only row 0 uses it, and only for
         // columns < nx; the runs reach into the tables' padding past the row end)
         T in[K][U];
@@ -356,11 +391,11 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
                     }
                 }
             } else if constexpr (in_glob) {
-                if (seen_in < (D.tag | cin_hi)) seen_in = wait_progress_get(D.prog_in, D.tag | cin_hi, A.ctl, A.spin_limit);
+                if (seen_in < (D.tag | cin_hi)) seen_in = wait_progress_get(D.prog_in, D.tag | cin_hi, A.ctl, A.spin_limit, A.wait_ticks);
 #pragma unroll
                 for (int k = 0; k < K; ++k) load_run_agent<T, U>(D.edge_in + (int64_t)(g * K + k) * D.pitch + t0, in[k]);
             } else {
-                if (seen_in < cin_hi) seen_in = lds_wait_get(&prod[wave - 1], cin_hi, A.ctl, A.spin_limit);
+                if (seen_in < cin_hi) seen_in = lds_wait_get(&prod[wave - 1], cin_hi, A.ctl, A.spin_limit, A.wait_ticks);
 #pragma unroll
                 for (int k = 0; k < K; ++k) load_run<T, U>(in_ring + (g * K + k) * RING + (t0 & (RING - 1)), in[k]);
             }
@@ -374,7 +409,7 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
         const int c_out = t0 - R;  // first exported column
         if (OUT == kOutRing && c_out + U > 0) {
             const int need = c_out + U - RING;
-            if (need > 0 && seen_out < need) seen_out = lds_wait_get(&cons[wave], need, A.ctl, A.spin_limit);
+            if (need > 0 && seen_out < need) seen_out = lds_wait_get(&cons[wave], need, A.ctl, A.spin_limit, A.wait_ticks);
         }
 
         // MODE 0: every lane inside its row; 1: lanes before their row start hold their x-face
@@ -387,12 +422,31 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const T dn = shift_up<R>(in[k][u], psi[k]);
-                const T num = fma(b[k], dn, fma(a[k], psi[k], cS[u]));
+                T src;
+                if constexpr (ANG) src = (T)cA[u][k];
+                else src = cS[u];
+                const T num = fma(b[k], dn, fma(a[k], psi[k], src));
                 const T v = num * rcp_fast(cst[u] + ab[k]);
                 if (MODE == 1) psi[k] = c >= 0 ? v : psi[k];
                 else psi[k] = v;
                 hist[k][u] = psi[k];
                 acc[u] = k == 0 ? w[k] * v : fma(w[k], v, acc[u]);
+            }
+            // dense kernels: the cell's weighted angular flux, K BF16 values per lane
+            if constexpr (ANG) {
+                if (row_ok && c >= 0 && c < nx) {
+                    uint16_t* const po = D.psi + obase + (rowbase + (XPOS ? c : nx - 1 - c)) * 16;
+                    if constexpr (K == 1) {
+                        *po = (uint16_t)bf16_bits(w[0] * psi[0]);
+                    } else {
+                        uint32_t pk[K / 2];
+#pragma unroll
+                        for (int k = 0; k < K; k += 2)
+                            pk[k / 2] = bf16_bits(w[k] * psi[k]) | (bf16_bits(w[k + 1] * psi[k + 1]) << 16);
+                        if constexpr (K == 2) *reinterpret_cast<uint32_t*>(po) = pk[0];
+                        else *reinterpret_cast<uint2*>(po) = make_uint2(pk[0], pk[1]);
+                    }
+                }
             }
         };
         const int mode = t0 < R ? 1 : (t0 + U <= nx ? 0 : 2);
@@ -461,11 +515,17 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
         }
 
         const int done = min(max(c_out + U, 0), nx);   // top-row columns exported so far
-        if (OUT == kOutEdge) stores_complete();         // the edge words have landed before publishing
+        // The band's top edge is published every EB blocks (16 steps) and at its last column:
+        // publishing waits for every memory operation of the wave to complete (the edge words
+        // must have landed), prefetched loads included, so doing it every block of a short
+        // block paced the whole band above by one memory round trip per block.
+        constexpr int EB = U >= 16 ? 1 : 16 / U;
+        const bool publish = OUT == kOutEdge && (((t0 / U) % EB) == EB - 1 || done >= nx);
+        if (publish) stores_complete();                 // the edge words have landed before publishing
         if (lane == 0) {
             if (!in_bc && !in_glob && t0 < nx)
                 lds_publish(&cons[wave - 1], cin_hi);
-            if (OUT == kOutEdge)
+            if (publish)
                 __hip_atomic_store(D.prog_out, D.tag | done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             else if (OUT == kOutRing)
                 lds_publish(&prod[wave], done);
@@ -477,46 +537,52 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
         for (int q = 0; q < PD; ++q) {
             const int tq = t0 + q * U;
             if (q == 0 || tq < tend) {
-                T cst[U], cS[U];
+                T cst[U], cS[ANG ? 1 : U];
+                VK cA[UA];
 #pragma unroll
-                for (int u = 0; u < U; ++u) {
-                    cst[u] = pst[q][u];
-                    cS[u] = pS[q][u];
+                for (int u = 0; u < U; ++u) cst[u] = pst[q][u];
+                if constexpr (ANG) {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) cA[u] = pA[q][u];
+                } else {
+#pragma unroll
+                    for (int u = 0; u < U; ++u) cS[u] = pS[q][u];
                 }
-                if (tq + PD * U < tsteps) fetch(pst[q], pS[q], tq + PD * U);
-                block(tq, cst, cS);
+                if (tq + PD * U < tsteps) fetch(pst[q], pS[q], pA[q], tq + PD * U);
+                block(tq, cst, cS, cA);
             }
         }
     }
 }
 
-template <typename T, int R, int K, int PD, bool XPOS>
+template <typename T, int R, int K, int PD, bool XPOS, bool ANG>
 __device__ __forceinline__ void diag_block_any(const DiagArgs& A, const DiagTask<T>& D, const int rb, const int wave, const int NB,
                                                T* ring, int* prod, int* cons,
                                                const T (&a)[K], const T (&b)[K], const T (&ab)[K], const T (&w)[K])
 {
     const int out = rb + 1 >= D.nblocks ? kOutNone : (wave == NB - 1 ? kOutEdge : kOutRing);
     if (rb == 0) {
-        if (out == kOutNone) diag_block<T, R, K, PD, XPOS, kInBoundary, kOutNone>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
-        else if (out == kOutEdge) diag_block<T, R, K, PD, XPOS, kInBoundary, kOutEdge>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
-        else diag_block<T, R, K, PD, XPOS, kInBoundary, kOutRing>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        if (out == kOutNone) diag_block<T, R, K, PD, XPOS, kInBoundary, kOutNone, ANG>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else if (out == kOutEdge) diag_block<T, R, K, PD, XPOS, kInBoundary, kOutEdge, ANG>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else diag_block<T, R, K, PD, XPOS, kInBoundary, kOutRing, ANG>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
     } else if (wave == 0) {
-        if (out == kOutNone) diag_block<T, R, K, PD, XPOS, kInEdge, kOutNone>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
-        else if (out == kOutEdge) diag_block<T, R, K, PD, XPOS, kInEdge, kOutEdge>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
-        else diag_block<T, R, K, PD, XPOS, kInEdge, kOutRing>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        if (out == kOutNone) diag_block<T, R, K, PD, XPOS, kInEdge, kOutNone, ANG>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else if (out == kOutEdge) diag_block<T, R, K, PD, XPOS, kInEdge, kOutEdge, ANG>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else diag_block<T, R, K, PD, XPOS, kInEdge, kOutRing, ANG>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
     } else {
-        if (out == kOutNone) diag_block<T, R, K, PD, XPOS, kInRing, kOutNone>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
-        else if (out == kOutEdge) diag_block<T, R, K, PD, XPOS, kInRing, kOutEdge>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
-        else diag_block<T, R, K, PD, XPOS, kInRing, kOutRing>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        if (out == kOutNone) diag_block<T, R, K, PD, XPOS, kInRing, kOutNone, ANG>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else if (out == kOutEdge) diag_block<T, R, K, PD, XPOS, kInRing, kOutEdge, ANG>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
+        else diag_block<T, R, K, PD, XPOS, kInRing, kOutRing, ANG>(A, D, rb, wave, ring, prod, cons, a, b, ab, w);
     }
 }
 
 // Persistent workgroups take (task, band) tickets in band-major order, so the band below a
 // ticket's band always holds an earlier ticket: every wait is on a workgroup that is running or
 // done.
-template <typename T, int R, int K, int PD>
+template <typename T, int R, int K, int PD, bool ANG>
 __global__ __launch_bounds__((64 * diag_max_waves<T, K, PD>())) void diag_kernel(DiagArgs A)
 {
+    static_assert(!ANG || sizeof(T) == 4, "dense-kernel row-lane sweeps are FP32 (BF16 angular flux)");
     constexpr int NG = kWave / R;
     constexpr int NO = NG * K;
     constexpr int RING = diag_ring<R>();
@@ -570,6 +636,13 @@ __global__ __launch_bounds__((64 * diag_max_waves<T, K, PD>())) void diag_kernel
             D.edge_out = (T*)A.edge + eoff + (int64_t)band * edge_len;
             D.prog_out = A.prog + poff + band;
             D.tag = tag;
+            if constexpr (ANG) {
+                const SystemDev& SD = A.sys[sys];
+                D.cells = (int64_t)D.nx * D.ny;
+                D.ang = (const float*)A.ang_src + uniform64(SD.ang_off);
+                D.psi = (uint16_t*)A.psi_out + uniform64(SD.ang_off);
+                D.ord0 = uniform(A.ords[ord_off].ord);
+            }
             const int rb = band * NB + wave;
             if (rb < D.nblocks) {
                 T a[K], b[K], ab[K], w[K];
@@ -581,8 +654,8 @@ __global__ __launch_bounds__((64 * diag_max_waves<T, K, PD>())) void diag_kernel
                     ab[k] = a[k] + b[k];
                     w[k] = to_T<T>(o.w);
                 }
-                if (quad == 0 || quad == 3) diag_block_any<T, R, K, PD, true>(A, D, rb, wave, NB, ring, prod, cons, a, b, ab, w);
-                else diag_block_any<T, R, K, PD, false>(A, D, rb, wave, NB, ring, prod, cons, a, b, ab, w);
+                if (quad == 0 || quad == 3) diag_block_any<T, R, K, PD, true, ANG>(A, D, rb, wave, NB, ring, prod, cons, a, b, ab, w);
+                else diag_block_any<T, R, K, PD, false, ANG>(A, D, rb, wave, NB, ring, prod, cons, a, b, ab, w);
             }
         }
         __syncthreads();  // the band is done before its LDS is reused
@@ -590,7 +663,7 @@ __global__ __launch_bounds__((64 * diag_max_waves<T, K, PD>())) void diag_kernel
     if (lane == 0) atomicMax(&A.ctl->t_last, (unsigned long long)wall_clock64());
 }
 
-template <typename T, int R, int K, int PD>
+template <typename T, int R, int K, int PD, bool ANG = false>
 hipError_t launch_diag_t(const DiagArgs& a, int grid, int nb, hipStream_t s)
 {
     constexpr int NO = (kWave / R) * K;
@@ -598,11 +671,11 @@ hipError_t launch_diag_t(const DiagArgs& a, int grid, int nb, hipStream_t s)
     const size_t lds = sizeof(T) * (size_t)(nb - 1) * diag_ring<R>() * NO + sizeof(int) * (2 * kDiagMaxWaves + 1);
     if (lds > 160 * 1024) return hipErrorInvalidValue;
     if (lds > 64 * 1024) {
-        const hipError_t e = hipFuncSetAttribute((const void*)diag_kernel<T, R, K, PD>,
+        const hipError_t e = hipFuncSetAttribute((const void*)diag_kernel<T, R, K, PD, ANG>,
                                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
         if (e != hipSuccess) return e;
     }
-    hipLaunchKernelGGL((diag_kernel<T, R, K, PD>), dim3(grid), dim3(64 * nb), lds, s, a);
+    hipLaunchKernelGGL((diag_kernel<T, R, K, PD, ANG>), dim3(grid), dim3(64 * nb), lds, s, a);
     return hipGetLastError();
 }
 

@@ -32,6 +32,7 @@ struct SweepArgs {
     SysCtl* sysctl;
     int32_t mom_r;             // linear kernel: 1 = also form the 1/r-weighted density (plane 3)
     int32_t pad;
+    int64_t wait_ticks;        // real-time clock ticks before a dependency wait gives up
 };
 
 struct DiagArgs {
@@ -53,6 +54,9 @@ struct DiagArgs {
     const void* inflow;        // unweighted boundary inflow pool (T)
     Ctl* ctl;
     SysCtl* sysctl;
+    const void* ang_src;       // dense kernels: per-ordinate source pool, ordinate blocks of 16
+    void* psi_out;             // dense kernels: weighted angular flux pool (BF16), same layout
+    int64_t wait_ticks;        // real-time clock ticks before a dependency wait gives up
 };
 
 struct CombineArgs {
@@ -107,6 +111,10 @@ struct ContractArgs {
     int32_t M, N, K;
     int32_t sys_index;
     const SysCtl* sysctl;      // skip when that system has stopped (NULL: always run)
+    int32_t blocked;           // BF16 kernel: 1 = A and out in ordinate blocks of 16,
+                               // [K / 16][M][16] and [N / 16][M][16] (the row-lane sweep's
+                               // layout); 0 = row-major [M][K] and [M][N]
+    int32_t pad;
 };
 
 // Slab systems (Sec. 4.1): all share one problem (fields at the nn grid points), each has its own
@@ -141,10 +149,11 @@ size_t sweep_lds_bytes(bool fp64, int tx, int ty, bool ang, int L, int nw, int m
 // Row-lane sweep: R rows per lane block (16 or 64), K ordinates per lane (1, 2, 4; FP64: 1, 2),
 // nb wavefronts (row blocks) per workgroup (1..16; 1..8 when K * sizeof(T) >= 16), persistent
 // workgroups taking (task, band) tickets.
+// ang: per-ordinate sources in, BF16 weighted angular flux out (dense kernels; FP32 only).
 bool diag_supported(bool fp64, int R, int K);
-int diag_max_nb(bool fp64, int K);
+int diag_max_nb(bool fp64, int K, bool ang = false);
 size_t diag_lds_bytes(bool fp64, int R, int K, int nb);
-hipError_t launch_diag(const DiagArgs& a, int grid, int nb, bool fp64, int R, int K, hipStream_t s);
+hipError_t launch_diag(const DiagArgs& a, int grid, int nb, bool fp64, int R, int K, bool ang, hipStream_t s);
 hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s);
 hipError_t launch_sweep_prologue(Ctl* ctl, hipStream_t s);
 hipError_t launch_mark(Ctl* ctl, hipStream_t s);

@@ -589,7 +589,14 @@ __device__ __forceinline__ void contract_bf16_tile(const ContractArgs& A, const 
     typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
     u32x4 ra[kStage], rb[kStage];
     const int row0 = tid / kSegs, seg = tid % kSegs;
-    auto a_at = [&](const int h) { return Ag + (int64_t)min(m0 + row0 + kRowStep * h, A.M - 1) * A.K + seg * 8; };
+    // element k of row m: row-major m * K + k, or blocked ((k / 16) * M + m) * 16 + k % 16 (a
+    // 16-byte segment never straddles a block); a_at(h) + d(k0) addresses K step k0
+    const bool blocked = A.blocked != 0;
+    auto a_at = [&](const int h) {
+        const int64_t m = min(m0 + row0 + kRowStep * h, A.M - 1);
+        return blocked ? Ag + ((int64_t)(seg / 2) * A.M + m) * 16 + (seg % 2) * 8 : Ag + m * A.K + seg * 8;
+    };
+    const int64_t a_kstep = blocked ? (int64_t)(GK / 16) * A.M * 16 : GK;  // advance of one K step
     const __bf16* __restrict__ pb = Bg + (int64_t)(n0 + row0) * A.K + seg * 8;
     const int64_t sb = kRowStep * (int64_t)A.K;
 #pragma unroll
@@ -607,7 +614,7 @@ __device__ __forceinline__ void contract_bf16_tile(const ContractArgs& A, const 
         if (k0 + GK < A.K) {
 #pragma unroll
             for (int h = 0; h < kStage; ++h) {
-                ra[h] = *(const u32x4*)(a_at(h) + k0 + GK);
+                ra[h] = *(const u32x4*)(a_at(h) + (k0 / GK + 1) * a_kstep);
                 rb[h] = *(const u32x4*)(pb + h * sb + k0 + GK);
             }
         }
@@ -643,7 +650,8 @@ __device__ __forceinline__ void contract_bf16_tile(const ContractArgs& A, const 
             for (int e = 0; e < 16; ++e) {
                 const int rl = wm * 64 + x * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
                 const int row = m0 + rl;
-                if (row < A.M) out[(int64_t)row * A.N + col] = fmaf(ss_q[0][rl], acc[x][y][e], ss_q[1][rl]);
+                const int64_t at = blocked ? ((int64_t)(col / 16) * A.M + row) * 16 + col % 16 : (int64_t)row * A.N + col;
+                if (row < A.M) out[at] = fmaf(ss_q[0][rl], acc[x][y][e], ss_q[1][rl]);
             }
         }
     }
@@ -776,13 +784,13 @@ hipError_t launch_sweep(const SweepArgs& a, int grid, bool fp64, int tx, int ty,
     return hipErrorInvalidValue;
 }
 
-hipError_t launch_diag_f32(const DiagArgs&, int, int, int, int, hipStream_t);
+hipError_t launch_diag_f32(const DiagArgs&, int, int, int, int, bool, hipStream_t);
 hipError_t launch_diag_f64(const DiagArgs&, int, int, int, int, hipStream_t);
 
-int diag_max_nb(bool fp64, int K)
+int diag_max_nb(bool fp64, int K, bool ang)
 {
     (void)fp64;
-    return K > 1 ? 8 : kDiagMaxWaves;
+    return (K > 1 || ang) ? 8 : kDiagMaxWaves;  // as diag_max_waves: two prefetch sets or K > 1
 }
 
 bool diag_supported(bool fp64, int R, int K)
@@ -798,10 +806,10 @@ size_t diag_lds_bytes(bool fp64, int R, int K, int nb)
     return (fp64 ? 8 : 4) * (size_t)(nb - 1) * ring * no + sizeof(int) * (2 * kDiagMaxWaves + 1);
 }
 
-hipError_t launch_diag(const DiagArgs& a, int grid, int nb, bool fp64, int R, int K, hipStream_t s)
+hipError_t launch_diag(const DiagArgs& a, int grid, int nb, bool fp64, int R, int K, bool ang, hipStream_t s)
 {
-    if (!diag_supported(fp64, R, K)) return hipErrorInvalidValue;
-    return fp64 ? launch_diag_f64(a, grid, nb, R, K, s) : launch_diag_f32(a, grid, nb, R, K, s);
+    if (!diag_supported(fp64, R, K) || (ang && fp64)) return hipErrorInvalidValue;
+    return fp64 ? launch_diag_f64(a, grid, nb, R, K, s) : launch_diag_f32(a, grid, nb, R, K, ang, s);
 }
 
 hipError_t launch_combine(const CombineArgs& a, int nblocks, bool fp64, hipStream_t s)

@@ -156,8 +156,25 @@ __device__ __forceinline__ void store_partials(const RowCtx& R, double (&acc)[TX
 // strips of one wave-stream: wave k sweeps strip band*NW + k.  Edges between strips of a band go
 // through LDS ring buffers (RB chunk slots per boundary, produced / consumed counters in LDS);
 // only the band's top edge goes to global memory for the next band, behind a progress counter.
+#ifndef ROM_SWEEP_DEFER
+#define ROM_SWEEP_DEFER 0
+#endif
+
+// Waves per SIMD the compiler must leave room for.  The FP32 isotropic flux-only step sweeps fit
+// four waves in 128 VGPRs without spilling (tiles of up to 128 cells, and 16 x 16 with 64-lane
+// groups); the extra wave hides the LDS and hand-off waits of the row loop (c5 sweep 58.3 ->
+// 53.9 ms per solve).  Every other variant would spill at that bound and keeps the compiler's
+// own register budget.
 template <typename T, int TX, int TY, bool DD, bool ANG, int PSI, int L, int MOM>
-__global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
+constexpr int sweep_waves_per_simd()
+{
+    return (sizeof(T) == 4 && !DD && !ANG && PSI == 0 && MOM == 1 && (TX * TY <= 128 || L == 64)) ? 4 : 1;
+}
+
+template <typename T, int TX, int TY, bool DD, bool ANG, int PSI, int L, int MOM>
+__global__ __launch_bounds__(64 * kMaxBand)
+__attribute__((amdgpu_waves_per_eu(sweep_waves_per_simd<T, TX, TY, DD, ANG, PSI, L, MOM>())))
+void sweep_kernel(SweepArgs A)
 {
     static_assert(MOM == 1 || (MOM == 4 && !ANG && PSI == 0), "moment sweeps take staged sources only");
     constexpr int G = kWave / L;  // lane groups per wavefront
@@ -351,13 +368,13 @@ __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
                     for (int i = 0; i < TX; ++i)
                         yd[i] = (yin_off >= 0 && i < cols) ? inflow[yin_off + (int64_t)(i0 + i) * kWave + lane] : T(0);
                 } else if (from_global) {
-                    wait_progress(prog_below, tag | (long long)(c + 1), A.ctl, A.spin_limit);
+                    wait_progress(prog_below, tag | (long long)(c + 1), A.ctl, A.spin_limit, A.wait_ticks);
 #pragma unroll
                     for (int i = 0; i < TX; ++i)
                         yd[i] = (i < cols) ? edge_load(edge_below + (int64_t)(i0 + i) * kWave + lane) : T(0);
                 } else {
                     // from the wave below in this band, through its LDS ring
-                    lds_wait(&produced[wave - 1], c + 1, A.ctl, A.spin_limit);
+                    lds_wait(&produced[wave - 1], c + 1, A.ctl, A.spin_limit, A.wait_ticks);
                     const T* slot = ring[wave - 1][c % RB];
 #pragma unroll
                     for (int i = 0; i < TX; ++i) yd[i] = slot[i * kWave + lane];
@@ -447,10 +464,62 @@ __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
                         store_partials<TX, L>(R, acc, my_part);
                     }
                 };
+                // Isotropic flux-only step sweeps (the deferred form): a row's values are the
+                // next row's y-face inputs, and the lane reduction that forms the row's scalar
+                // flux overwrites its operands (the permlane swaps), so reducing a row while its
+                // values are still needed costs a copy of each.  Instead the rows alternate
+                // between two banks and each row is reduced once the next row has read it; the
+                // chunk's last row is reduced after it has left as the strip's top edge.
+                constexpr bool DEFER = ROM_SWEEP_DEFER && !DD && !ANG && MOM == 1 && PSI == 0;
+                T ydB[DEFER ? TX : 1];
+                auto row_update = [&](const int r, const T (&yin)[TX], T (&yout)[TX]) {
+                    T Sv[TX];
+#pragma unroll
+                    for (int i = 0; i < TX; ++i) Sv[i] = lds_S[wave][g][r * TX + i];
+                    T xf = xl[r];
+                    if ((umask >> r) & 1) {
+                        const T rr = rcp_fast(lds_st[wave][r * TX] + kappa);
+                        const T wr = w * rr, ar = a * rr, br = b * rr;
+#pragma unroll
+                        for (int i = 0; i < TX; ++i) {
+                            xf = fma(br, yin[i], fma(ar, xf, wr * Sv[i]));
+                            yout[i] = xf;
+                        }
+                    } else {
+#pragma unroll
+                        for (int i = 0; i < TX; ++i) {
+                            const T rr = rcp_fast(lds_st[wave][r * TX + i] + kappa);
+                            xf = fma(b, yin[i], fma(a, xf, w * Sv[i])) * rr;
+                            yout[i] = xf;
+                        }
+                    }
+                    xl[r] = xf;
+                };
+                auto row_reduce = [&](const int r, T (&vals)[TX]) {
+                    const int jj = j0 + r;
+                    const int j = ypos ? jj : ny - 1 - jj;
+                    const RowCtx R{lane, g, (int64_t)j * nx, i0, nx, xpos, cols};
+                    store_partials<TX, L>(R, vals, my_part);
+                };
                 if constexpr (ANG) {
 #pragma unroll
                     for (int r = 0; r < TY; ++r)
                         if (r < rows) do_row(r);
+                } else if constexpr (DEFER) {
+                    int r = 0;
+                    for (; r + 1 < rows; r += 2) {
+                        row_update(r, yd, ydB);
+                        if (r > 0) row_reduce(r - 1, yd);  // yd held row r - 1 (the chunk's inflow at r = 0)
+                        row_update(r + 1, ydB, yd);
+                        row_reduce(r, ydB);
+                    }
+                    if (r < rows) {  // an odd row count (a ragged strip): the last row
+                        row_update(r, yd, ydB);
+                        if (r > 0) row_reduce(r - 1, yd);
+#pragma unroll
+                        for (int i = 0; i < TX; ++i) yd[i] = ydB[i];
+                    }
+                    // yd now holds the chunk's last row: its top edge, reduced below once sent
                 } else {
                     int r = 0;
                     if constexpr (MOM == 1 && PSI == 0) {
@@ -473,12 +542,13 @@ __global__ __launch_bounds__(64 * kMaxBand) void sweep_kernel(SweepArgs A)
                         __hip_atomic_store(prog_mine, tag | (long long)(c + 1), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
                 } else if (has_out) {
                     // to the wave above in this band: wait until it has consumed slot c - RB
-                    if (c >= RB) lds_wait(&consumed[wave], c + 1 - RB, A.ctl, A.spin_limit);
+                    if (c >= RB) lds_wait(&consumed[wave], c + 1 - RB, A.ctl, A.spin_limit, A.wait_ticks);
                     T* slot = ring[wave][c % RB];
 #pragma unroll
                     for (int i = 0; i < TX; ++i) slot[i * kWave + lane] = yd[i];
                     if (lane == 0) __hip_atomic_store(&produced[wave], c + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_WORKGROUP);
                 }
+                if constexpr (DEFER) row_reduce(rows - 1, yd);
             }
         }
         __syncthreads();  // the band is done before its LDS is reused

@@ -231,3 +231,94 @@ def test_autotune_picks_a_valid_kernel(R, orc):
     assert rc == 0 and st.sweep in (R.ROM_SWEEP_STRIP, R.ROM_SWEEP_DIAG)
     ref = orc.source_iterate(p, d, w, None, tol=1e-6)
     parity.check(phi, ref["phi"], 1e-5)
+
+
+# ------------------------------------------------------------------------------------ dense kernels
+# The row-lane sweep with per-ordinate sources: it reads the contraction's S[cell][npad] and writes
+# the weighted angular flux as BF16 for the next contraction.  Bar: the BF16 contraction's 2e-3.
+@pytest.mark.parametrize("rows,k", SHAPES)
+def test_dense_kernel_shapes_fixed_iterations(R, orc, rows, k):
+    """HG g = 0.8 (folded) on a grid ragged against the row blocks, isotropic inflow on every face,
+    quadrants with fewer ordinates than a task holds; four iterations on both sides."""
+    rng = np.random.default_rng(303)
+    nx, ny = 45, 70
+    st, ss, q = rand_problem(rng, nx, ny, 0.8)
+    inflow = {"left": rng.uniform(0, 1, ny), "right": rng.uniform(0, 1, ny), "bottom": rng.uniform(0, 1, nx),
+              "top": rng.uniform(0, 1, nx)}
+    h = R.Handle(nx, ny, st, ss, q, box=(0.0, 1.3, 0.0, 0.7), inflow=inflow)
+    p = orc.Problem(nx, ny, st, ss, q, box=(0.0, 1.3, 0.0, 0.7), inflow=inflow)
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 3, 5, seed=8, sample=2)  # 15 per quadrant
+    h.set_ordinates(d, w)
+    h.set_scattering(R.ROM_SCAT_HG, 0.8)
+    phi, st_, rc = h.source_iterate(diag_opts(R, "fp32", rows, k, tol=-1.0, max_iter=4))
+    assert rc == R.ROM_NOT_CONVERGED and st_.iters == 4 and st_.sweep == R.ROM_SWEEP_DIAG
+    W = orc.build_W(d, w, orc.SCAT_HG, 0.8, fold=1)
+    ref = orc.source_iterate(p, d, w, W, tol=-1.0, max_iter=4)
+    parity.check(phi, ref["phi"], 2e-3, what=f"rows {rows} k {k}")
+
+
+def test_dense_kernel_c4_path(R, orc):
+    """The c4 ordinate set (1024 stratified ordinates, HG g = 0.8) on 128 x 128 cells with the
+    row-lane sweep (16 rows x 4 ordinates per lane): three iterations against the oracle, and to
+    convergence against the strip sweep's solve."""
+    g = RI.uniform_fields(128, 128, 1.0, 0.8, 0.45, 0.55)
+    h = R.Handle(g.nx, g.ny, g.sigma_t, g.sigma_s, g.q)
+    h.set_scattering(R.ROM_SCAT_HG, 0.8)
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 16, 16, seed=0)
+    h.set_ordinates(d, w)
+    phi, st_, rc = h.source_iterate(diag_opts(R, "fp32", 16, 4, tol=-1.0, max_iter=3))
+    assert rc == R.ROM_NOT_CONVERGED and st_.iters == 3
+    p = orc.Problem(g.nx, g.ny, g.sigma_t, g.sigma_s, g.q)
+    W = orc.build_W(d, w, orc.SCAT_HG, 0.8, fold=1)
+    ref = orc.source_iterate(p, d, w, W, tol=-1.0, max_iter=3)
+    parity.check(phi, ref["phi"], 2e-3, what="c4 path, row-lane")
+    conv, st_c, rc = h.source_iterate(diag_opts(R, "fp32", 16, 4, tol=1e-6))
+    strip, st_s, rc2 = h.source_iterate(R.si_opts(tol=1e-6, tile=(8, 4), band=4, sweep=R.ROM_SWEEP_STRIP))
+    assert rc == 0 and rc2 == 0 and abs(st_c.iters - st_s.iters) <= 1
+    parity.check(conv, strip, 2e-3, what="row-lane vs strip, converged")
+
+
+def test_dense_caller_kernel_and_reuse(R, orc):
+    """A non-symmetric caller kernel with unequal weights (pins the orientation of the contraction
+    through the row-lane layout), then new ordinate values for the cached plan (refresh: lane
+    table, inflow and kernel matrix rewritten in place)."""
+    rng = np.random.default_rng(31)
+    nx, ny = 33, 20
+    st, ss, q = rand_problem(rng, nx, ny, 0.6)
+    h = R.Handle(nx, ny, st, ss, q)
+    p = orc.Problem(nx, ny, st, ss, q)
+    d, w = R.generate_ordinates(R.ROM_ORD_GAUSS2D, 4)
+    h.set_ordinates(d, w)
+    P = rng.uniform(0.2, 1.5, (len(w), len(w)))
+    h.set_scattering(R.ROM_SCAT_DENSE, 0.0, P)
+    o = diag_opts(R, "fp32", 16, 2, tol=-1.0, max_iter=5)
+    phi, _, _ = h.source_iterate(o)
+    W = orc.build_W(d, w, orc.SCAT_DENSE, P=P)
+    parity.check(phi, orc.source_iterate(p, d, w, W, tol=-1.0, max_iter=5)["phi"], 2e-3, what="dense P")
+    h.set_scattering(R.ROM_SCAT_HG, 0.6)
+    for sample in (0, 1):
+        d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 3, 3, seed=4, sample=sample)
+        h.set_ordinates(d, w)
+        phi, st_, _ = h.source_iterate(o)
+        assert st_.sweep == R.ROM_SWEEP_DIAG
+        W = orc.build_W(d, w, orc.SCAT_HG, 0.6, fold=1)
+        parity.check(phi, orc.source_iterate(p, d, w, W, tol=-1.0, max_iter=5)["phi"], 2e-3, what=f"sample {sample}")
+
+
+def test_dense_kernel_ensemble(R, orc):
+    """An ensemble of HG samples (normalized kernel) on the row-lane sweep: each sample's flux
+    against the oracle at the GPU's iteration count."""
+    f = RI.uniform_fields(40, 36, 1.0, 0.8, 0.45, 0.55)
+    h = R.Handle(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    p = orc.Problem(f.nx, f.ny, f.sigma_t, f.sigma_s, f.q)
+    h.set_scattering(R.ROM_SCAT_HG | R.ROM_SCAT_NORMALIZE, 0.8)
+    o = diag_opts(R, "fp32", 16, 1, tol=1e-6)
+    phis, st_, rc = h.ensemble_samples(6, 3, R.ROM_ORD_STRATIFIED, 2, 2, opts=o)
+    assert rc == 0 and st_.sweep == R.ROM_SWEEP_DIAG
+    for k in range(6):
+        d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 2, 2, seed=3, sample=k)
+        W = orc.build_W(d, w, orc.SCAT_HG | orc.SCAT_NORMALIZE, 0.8, fold=1)
+        ref = orc.source_iterate(p, d, w, W, tol=1e-6)
+        # each sample stops on its own; a stop one iteration apart moves phi by at most tol * max phi
+        assert st_.min_iters - 1 <= ref["iters"] <= st_.max_iters + 1
+        parity.check(phis[k], ref["phi"], 2e-3, what=f"sample {k}")
