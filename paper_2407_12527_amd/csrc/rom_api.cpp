@@ -316,8 +316,10 @@ struct Plan {
     int64_t inflow_len = 0;                 // elements of the weighted inflow table (0: vacuum)
     std::vector<double> h_inflow;           // host copies kept for stream-ordered rewrites
     std::vector<float> h_inflow32;
-    std::vector<double> h_bt64;
-    std::vector<uint16_t> h_bt16;
+    std::vector<KmSys> h_kmsys;             // kernel-matrix jobs and their ordinate tables (host
+    std::vector<double> h_kmord;            // copies kept until the stream-ordered uploads are done)
+    std::vector<int32_t> h_kmuidx;
+    std::vector<double> h_kmdense;
     int prog_count = 0;  // progress counters (64-bit words)
     int cells_per_block = 1024;
     int many_cpt = 0;  // many-slot combine: cells per thread (0: the few-slot combine)
@@ -331,6 +333,7 @@ struct Plan {
     DevMem d_probs, d_sys, d_ws, d_lanes, d_tickets, d_slot_off, d_slot_order, d_slot_off_ord, d_cblocks;
     DevMem d_st, d_ss, d_q, d_src, d_phi, d_part, d_edge, d_inflow, d_prog, d_ctl, d_sysctl, d_rhist;
     DevMem d_ang, d_psi, d_Pt, d_uflags;
+    DevMem d_kmsys, d_kmord, d_kmuidx, d_kmdense, d_kminv;  // kernel-matrix build inputs
     DevMem d_citems, d_cmap;  // batched contraction: per-system arguments, (system, block) map
     int cmap_blocks = 0;
     std::vector<int64_t> pt_off;  // per system offset into d_Pt (elements)
@@ -1159,58 +1162,76 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     }
 }
 
-// P^T in internal order for every system: Bt[n][k] = P(u_k, u_n), zero on padding.
-void build_kernel_matrices(Plan& P, const std::vector<SysInput>& in, hipStream_t rewrite_on = nullptr)
+// P^T in internal order for every system: Bt[n][k] = P(u_k, u_n) / r_k, zero on padding, built on
+// the device (launch_kernel_matrix) from the ordinate tables uploaded here (32 bytes per ordinate;
+// the caller's dense kernel as well for ROM_SCAT_DENSE), stream-ordered on s.  The first call of a
+// plan places the buffers; later calls (new ordinates of the same structure) rewrite them in place.
+void build_kernel_matrices(Plan& P, const std::vector<SysInput>& in, hipStream_t s)
 {
-    int64_t total = 0;
+    const bool first = !P.d_kmsys.p;
+    int64_t total = 0, entries = 0, dtotal = 0;
+    int max_al = 0;
     P.pt_off.resize(P.nsys);
-    for (int s = 0; s < P.nsys; ++s) {
-        P.pt_off[s] = total;
-        total += (int64_t)P.npad_al[s] * P.npad_al[s];
+    P.h_kmsys.assign(P.nsys, KmSys{});
+    for (int k = 0; k < P.nsys; ++k) {
+        rom_handle* h = in[k].h;
+        KmSys& ks = P.h_kmsys[k];
+        ks.ord_off = entries;
+        ks.pt_off = P.pt_off[k] = total;
+        ks.npad = (int)P.user_of[k].size();
+        ks.al = P.npad_al[k];
+        ks.n = in[k].n;
+        ks.kind = h->scat;
+        ks.norm = h->scat_norm ? 1 : 0;
+        ks.g = h->g;
+        ks.dense_off = h->scat == ROM_SCAT_DENSE ? dtotal : 0;
+        if (h->scat == ROM_SCAT_DENSE) dtotal += (int64_t)in[k].n * in[k].n;
+        entries += ks.npad;
+        total += (int64_t)ks.al * ks.al;
+        max_al = std::max(max_al, ks.al);
     }
-    std::vector<double>& bt64 = P.h_bt64;
-    std::vector<uint16_t>& bt16 = P.h_bt16;
-    if (P.fp64) bt64.assign(total, 0.0);
-    else bt16.assign(total, 0);
-    for (int s = 0; s < P.nsys; ++s) {
-        rom_handle* h = in[s].h;
-        const int al = P.npad_al[s];
-        const auto& uo = P.user_of[s];
-        const int npad = (int)uo.size();
-        auto kernel = [&](int uk, int un) {  // P(u_uk incoming, u_un outgoing)
-            if (h->scat == ROM_SCAT_DENSE) return h->Pdense[(size_t)uk * h->n + un];
-            return phase_folded(h->scat, h->g, in[s].dirs + 3 * uk, in[s].dirs + 3 * un);
-        };
-        // normalized kernel: row uk divided by r_uk = sum over outgoing un of w_un P(uk, un)
-        std::vector<double> inv_r(in[s].n, 1.0);
-        if (h->scat_norm) {
-            for (int uk = 0; uk < in[s].n; ++uk) {
-                double r = 0.0;
-                for (int un = 0; un < in[s].n; ++un) r += in[s].w[un] * kernel(uk, un);
-                if (!(r > 0.0)) throw Fail{ROM_E_DOMAIN, "normalized kernel: a row sum is not positive"};
-                inv_r[uk] = 1.0 / r;
-            }
+    P.h_kmord.assign(entries * 4, 0.0);
+    P.h_kmuidx.assign(entries, -1);
+    P.h_kmdense.assign(std::max<int64_t>(dtotal, 1), 0.0);
+    for (int k = 0; k < P.nsys; ++k) {
+        const KmSys& ks = P.h_kmsys[k];
+        const auto& uo = P.user_of[k];
+        for (int i = 0; i < ks.npad; ++i) {
+            const int u = uo[i];
+            if (u < 0) continue;
+            P.h_kmuidx[ks.ord_off + i] = u;
+            double* o = &P.h_kmord[(ks.ord_off + i) * 4];
+            o[0] = in[k].dirs[3 * u];
+            o[1] = in[k].dirs[3 * u + 1];
+            o[2] = in[k].dirs[3 * u + 2];
+            o[3] = in[k].w[u];
         }
-        for (int nn = 0; nn < npad; ++nn) {
-            const int un = uo[nn];
-            if (un < 0) continue;
-            for (int kk = 0; kk < npad; ++kk) {
-                const int uk = uo[kk];
-                if (uk < 0) continue;
-                const double pv = kernel(uk, un) * inv_r[uk];
-                const int64_t idx = P.pt_off[s] + (int64_t)nn * al + kk;
-                if (P.fp64) bt64[idx] = pv;
-                else bt16[idx] = f32_to_bf16((float)pv);
-            }
-        }
+        if (in[k].h->scat == ROM_SCAT_DENSE)
+            std::copy(in[k].h->Pdense.begin(), in[k].h->Pdense.end(), P.h_kmdense.begin() + ks.dense_off);
     }
-    if (rewrite_on) {
-        if (P.fp64) rewrite(P.d_Pt, bt64, rewrite_on);
-        else rewrite(P.d_Pt, bt16, rewrite_on);
-    } else {
-        if (P.fp64) upload(P.d_Pt, bt64);
-        else upload(P.d_Pt, bt16);
+    if (first) {
+        take(P, P.d_Pt, total * (P.fp64 ? 8 : 2));
+        take(P, P.d_kmsys, P.h_kmsys.size() * sizeof(KmSys));
+        take(P, P.d_kmord, P.h_kmord.size() * sizeof(double));
+        take(P, P.d_kmuidx, P.h_kmuidx.size() * sizeof(int32_t));
+        take(P, P.d_kmdense, P.h_kmdense.size() * sizeof(double));
+        take(P, P.d_kminv, entries * sizeof(double));
     }
+    rewrite(P.d_kmsys, P.h_kmsys, s);
+    rewrite(P.d_kmord, P.h_kmord, s);
+    rewrite(P.d_kmuidx, P.h_kmuidx, s);
+    if (dtotal > 0) rewrite(P.d_kmdense, P.h_kmdense, s);
+    KmArgs a{};
+    a.sys = (const KmSys*)P.d_kmsys.p;
+    a.ord = (const double*)P.d_kmord.p;
+    a.uidx = (const int32_t*)P.d_kmuidx.p;
+    a.dense = (const double*)P.d_kmdense.p;
+    a.inv_r = (double*)P.d_kminv.p;
+    a.bt = P.d_Pt.p;
+    a.nsys = P.nsys;
+    a.fp64 = P.fp64 ? 1 : 0;
+    a.max_al = max_al;
+    HIPCHK(launch_kernel_matrix(a, s));
 }
 
 // New ordinate values (and inflow or kernel values) for a plan whose structure still fits: the
@@ -1226,6 +1247,9 @@ bool refresh_ordinates(Plan& P, const std::vector<SysInput>& in, hipStream_t s)
         if (scat_mode(si.h) == 1 && si.h->scat_norm) mom_r = 1;
     }
     if (mom_r != P.mom_r) return false;
+    if (P.aniso)  // the caller's dense kernel has a buffer of its own in the kernel-matrix inputs
+        for (size_t k = 0; k < in.size(); ++k)
+            if ((in[k].h->scat == ROM_SCAT_DENSE) != (P.h_kmsys[k].kind == ROM_SCAT_DENSE)) return false;
     std::vector<std::array<std::vector<int>, 4>> ql(in.size());
     for (size_t k = 0; k < in.size(); ++k) {
         if (in[k].h != P.handles[P.sys[k].prob]) return false;
@@ -1748,6 +1772,10 @@ int rom_set_scattering(rom_handle* h, int32_t kind, double g, const double* P)
         const size_t nn = (size_t)h->n * h->n;
         for (size_t k = 0; k < nn; ++k)
             if (!isfin(P[k]) || P[k] < 0.0) return fail(h, ROM_E_DOMAIN, "P must be finite and >= 0");
+        if (norm)  // weights are positive: a weighted row sum is positive unless the row is zero
+            for (int r = 0; r < h->n; ++r)
+                if (std::all_of(P + (size_t)r * h->n, P + (size_t)(r + 1) * h->n, [](double v) { return v == 0.0; }))
+                    return fail(h, ROM_E_DOMAIN, "normalized kernel: a row sum is not positive");
         h->Pdense.assign(P, P + nn);
     } else {
         h->Pdense.clear();
@@ -2099,7 +2127,7 @@ int solve_systems(rom_handle* owner, std::vector<SysInput>& in, const rom_si_opt
         slot.reset(new Plan());
         build_plan(*slot, in, o, smode, o.max_iter);
         if (aniso) {
-            build_kernel_matrices(*slot, in);
+            build_kernel_matrices(*slot, in, owner->stream());
             build_contract_batch(*slot);
         }
     }

@@ -117,6 +117,34 @@ struct ContractArgs {
     int32_t pad;
 };
 
+// One system's transposed scattering matrix Bt[n][k] = P(u_k, u_n) / r_k: the discrete kernel of
+// Sec. 2 taken at the ordinates themselves (the choice of Sec. 3.1), incoming u_k and outgoing u_n,
+// each row divided by its weighted sum r_k when the kernel is normalized (else r_k = 1), indexed by
+// the plan's internal ordinate order, zero on padding.
+struct KmSys {
+    int64_t ord_off;     // first entry of the system in the ordinate tables
+    int64_t pt_off;      // first element of its matrix ([al][al])
+    int64_t dense_off;   // first element of the caller's dense kernel ([n][n], caller's order)
+    int32_t npad;        // internal ordinates (padding included)
+    int32_t al;          // matrix side (>= npad; rows and columns past npad are zero)
+    int32_t n;           // caller's ordinate count
+    int32_t kind;        // 2 Henyey-Greenstein (projected to x-y, folded over z), 3 dense
+    int32_t norm;        // 1: divide by the weighted row sums
+    int32_t pad;
+    double g;
+};
+
+struct KmArgs {
+    const KmSys* sys;    // [nsys]
+    const double* ord;   // [entries][4]: direction (c, s, z) and weight of each internal ordinate
+    const int32_t* uidx; // [entries]: the caller's index of each internal ordinate, -1 on padding
+    const double* dense; // caller's dense kernels (kind 3), else unused
+    double* inv_r;       // [entries]: 1 / r_k (written when norm)
+    void* bt;            // matrices: BF16 bits (fp64 = 0) or doubles
+    int32_t nsys, fp64;
+    int32_t max_al, pad;
+};
+
 // Slab systems (Sec. 4.1): all share one problem (fields at the nn grid points), each has its own
 // n ordinates; a wavefront holds 64 / L systems of L lanes, a lane carries ordinates r, r + L, ...
 struct SlabArgs {
@@ -174,5 +202,7 @@ hipError_t launch_contract(const ContractArgs& a, int kind, hipStream_t s);  // 
 int contract_blocks(const ContractArgs& a, int kind);
 hipError_t launch_contract_batch(const ContractArgs* items, const int2* map, int nblocks, int kind, hipStream_t s);
 hipError_t launch_cast_bf16(const float* in, void* out, int64_t n, hipStream_t s);
+// Kernel matrices of every system of a plan (row sums first when a system is normalized).
+hipError_t launch_kernel_matrix(const KmArgs& a, hipStream_t s);
 
 }  // namespace rom

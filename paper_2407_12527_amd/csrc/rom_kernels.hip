@@ -8,7 +8,9 @@
 //   contract_*       anisotropic scattering source S = sigma_s (Psi' P) + q (eq. (3.1) right-hand
 //                    side with W = w P of eq. (3.4)): BF16 MFMA with FP32 accumulation, or a plain
 //                    tiled FP64/FP32 kernel for the FP64 path;
-//   moments_kernel   FP64 ensemble mean and unbiased variance over samples (eq. (4.6)).
+//   moments_kernel   FP64 ensemble mean and unbiased variance over samples (eq. (4.6));
+//   kernel_*_kernel  the transposed kernel matrices the contraction reads, built on the device from
+//                    the ordinates of each system (new ordinates every ROM sample).
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <stdint.h>
@@ -744,6 +746,71 @@ __global__ void cast_bf16_kernel(const float* __restrict__ in, __hip_bfloat16* _
         out[i] = __float2bfloat16(in[i]);
 }
 
+// ------------------------------------------------------------------------------ kernel matrix
+// Henyey-Greenstein kernel of the planar problem: the 3-D kernel at cos xi = u.v averaged over
+// the mirror image of v in the x-y plane (the z half of the sphere folded onto the other), the same
+// form the ordinates carry (c, s, z with the sweep using c, s only).
+__device__ __forceinline__ double km_hg(double g, double mu)
+{
+    const double d = 1.0 + g * g - 2.0 * g * mu;
+    return (1.0 - g * g) / (d * sqrt(d));
+}
+
+// P(u_k incoming, u_n outgoing) for valid internal ordinates k and n of system S.
+__device__ __forceinline__ double km_value(const KmArgs& A, const KmSys& S, int64_t k, int64_t n)
+{
+    if (S.kind == 3) {
+        const int uk = A.uidx[S.ord_off + k], un = A.uidx[S.ord_off + n];
+        return A.dense[S.dense_off + (int64_t)uk * S.n + un];
+    }
+    const double* a = A.ord + (S.ord_off + k) * 4;
+    const double* b = A.ord + (S.ord_off + n) * 4;
+    const double planar = a[0] * b[0] + a[1] * b[1];
+    const double zz = a[2] * b[2];
+    return 0.5 * (km_hg(S.g, planar + zz) + km_hg(S.g, planar - zz));
+}
+
+// 1 / r_k, r_k = sum_n w_n P(u_k, u_n), for every internal ordinate k of the normalized systems:
+// one wavefront per k, lanes over n in a fixed order, a fixed butterfly at the end.
+__global__ void __launch_bounds__(256) kernel_rowsum_kernel(KmArgs A)
+{
+    const KmSys S = A.sys[blockIdx.y];
+    const int k = blockIdx.x * 4 + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (!S.norm || k >= S.npad || A.uidx[S.ord_off + k] < 0) return;
+    double r = 0.0;
+    for (int n = lane; n < S.npad; n += 64)
+        if (A.uidx[S.ord_off + n] >= 0) r += A.ord[(S.ord_off + n) * 4 + 3] * km_value(A, S, k, n);
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) r += __shfl_xor(r, o, 64);
+    if (lane == 0) A.inv_r[S.ord_off + k] = 1.0 / r;
+}
+
+// Bt[n][k] = P(u_k, u_n) / r_k over the whole [al][al] matrix (zero where n or k is padding):
+// a block writes 4 rows n, threads along k (contiguous stores).
+__global__ void __launch_bounds__(256) kernel_fill_kernel(KmArgs A)
+{
+    const KmSys S = A.sys[blockIdx.y];
+    const int n0 = blockIdx.x * 4;
+    if (n0 >= S.al) return;
+    for (int e = threadIdx.x; e < 4 * S.al; e += 256) {
+        const int n = n0 + e / S.al, k = e % S.al;
+        if (n >= S.al) break;
+        double v = 0.0;
+        if (n < S.npad && k < S.npad && A.uidx[S.ord_off + n] >= 0 && A.uidx[S.ord_off + k] >= 0) {
+            v = km_value(A, S, k, n);
+            if (S.norm) v *= A.inv_r[S.ord_off + k];
+        }
+        const int64_t idx = S.pt_off + (int64_t)n * S.al + k;
+        if (A.fp64) {
+            static_cast<double*>(A.bt)[idx] = v;
+        } else {
+            const uint32_t u = __float_as_uint((float)v);  // round to nearest even, as the sweep's BF16 stores
+            static_cast<uint16_t*>(A.bt)[idx] = (uint16_t)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+        }
+    }
+}
+
 // ------------------------------------------------------------------------------------ launchers
 hipError_t launch_sweep_f32_8x4(const SweepArgs&, int, bool, bool, int, int, int, hipStream_t);
 hipError_t launch_sweep_f32_8x8(const SweepArgs&, int, bool, bool, int, int, int, hipStream_t);
@@ -998,6 +1065,15 @@ hipError_t launch_contract_batch(const ContractArgs* items, const int2* map, int
     if (kind == 0) hipLaunchKernelGGL(contract_bf16_batch_kernel, dim3(nblocks), dim3(256), 0, s, items, map);
     else if (kind == 1) hipLaunchKernelGGL(contract_plain_batch_kernel<float>, dim3(nblocks), dim3(256), 0, s, items, map);
     else hipLaunchKernelGGL(contract_plain_batch_kernel<double>, dim3(nblocks), dim3(256), 0, s, items, map);
+    return hipGetLastError();
+}
+
+hipError_t launch_kernel_matrix(const KmArgs& a, hipStream_t s)
+{
+    if (a.nsys < 1 || a.max_al < 1) return hipErrorInvalidValue;
+    const dim3 grid((a.max_al + 3) / 4, a.nsys);
+    hipLaunchKernelGGL(kernel_rowsum_kernel, grid, dim3(256), 0, s, a);
+    hipLaunchKernelGGL(kernel_fill_kernel, grid, dim3(256), 0, s, a);
     return hipGetLastError();
 }
 

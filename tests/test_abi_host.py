@@ -156,6 +156,11 @@ def test_handle_validation_without_device(R):
         assert R.rom_set_scattering(h, R.ROM_SCAT_HG, 0.8, None) == 0
         P = np.array([[1.0, -0.5], [0.2, 1.0]])
         assert R.rom_set_scattering(h, R.ROM_SCAT_DENSE, 0.0, P.ctypes.data) == R.ROM_E_DOMAIN
+        # a zero row has no weighted row sum to normalize by: refused when the kernel is set
+        Z = np.array([[0.0, 0.0], [0.2, 1.0]])
+        assert R.rom_set_scattering(h, R.ROM_SCAT_DENSE | R.ROM_SCAT_NORMALIZE, 0.0, Z.ctypes.data) == R.ROM_E_DOMAIN
+        assert R.rom_set_scattering(h, R.ROM_SCAT_DENSE, 0.0, Z.ctypes.data) == 0
+        assert R.rom_set_scattering(h, R.ROM_SCAT_HG, 0.8, None) == 0
         ang = -np.ones(2 * 3)
         assert R.rom_set_inflow_angular(h, R.ROM_FACE_LEFT, ang.ctypes.data) == R.ROM_E_DOMAIN
         assert R.rom_set_inflow_angular(h, 9, None) == R.ROM_E_ARG
