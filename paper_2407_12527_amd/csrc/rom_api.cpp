@@ -1399,12 +1399,13 @@ void build_contract_batch(Plan& P)
 void enqueue_iteration(Plan& P, hipStream_t s, double tol)
 {
     if (P.aniso) {
+        // the contraction's last block stamps the start of the sweep's timing (not the combine's end)
+        Ctl* const ctl = P.d_ctl.as<Ctl>();
         if (P.cmap_blocks > 0) {
-            HIPCHK(launch_contract_batch(P.d_citems.as<ContractArgs>(), P.d_cmap.as<int2>(), P.cmap_blocks, P.fp64 ? 2 : 0, s));
+            HIPCHK(launch_contract_batch(P.d_citems.as<ContractArgs>(), P.d_cmap.as<int2>(), P.cmap_blocks, P.fp64 ? 2 : 0, s, ctl));
         } else {
-            for (int k = 0; k < P.nsys; ++k) HIPCHK(launch_contract(contract_args(P, k), P.fp64 ? 2 : 0, s));
+            for (int k = 0; k < P.nsys; ++k) HIPCHK(launch_contract(contract_args(P, k), P.fp64 ? 2 : 0, s, ctl));
         }
-        HIPCHK(launch_mark(P.d_ctl.as<Ctl>(), s));  // the sweep is timed from here, not from the combine
     }
     HIPCHK(P.launch_sweep_any(0, s));
     const CombineArgs ca = P.combine_args(0, tol);

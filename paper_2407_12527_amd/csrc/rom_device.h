@@ -109,6 +109,8 @@ struct Ctl {
     int32_t active;         // systems still running after the last combine step
     int32_t error;          // 1: a dependency wait timed out
     int32_t sweeps;         // sweep launches that did work (timed)
+    int32_t cblocks_done;   // contraction blocks finished (the last one stamps t_mark)
+    int32_t pad;
     unsigned long long t_first;     // real-time clock at the first wave start of the running sweep
     unsigned long long t_last;      // ... and at the last wave end
     unsigned long long sweep_ticks; // summed sweep durations (real-time clock ticks)

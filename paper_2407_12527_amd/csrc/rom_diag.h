@@ -181,11 +181,14 @@ struct DiagTask {
     int ord0;            // the task's first ordinate
 };
 
-// BF16 bits of x, rounded to nearest even (x finite)
-__device__ __forceinline__ uint32_t bf16_bits(float x)
+// Two floats as packed BF16 (low half x), rounded to nearest even: one v_cvt_pk_bf16_f32 on gfx950.
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t bf16_pack(float x, float y)
 {
-    const uint32_t u = __float_as_uint(x);
-    return (u + 0x7fffu + ((u >> 16) & 1u)) >> 16;
+    bf16x2_t v;
+    v.x = (__bf16)x;
+    v.y = (__bf16)y;
+    return __builtin_bit_cast(uint32_t, v);
 }
 
 // U consecutive values at p (16-byte aligned) as 16-byte LDS or global accesses.
@@ -437,12 +440,11 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
                 if (row_ok && c >= 0 && c < nx) {
                     uint16_t* const po = D.psi + obase + (rowbase + (XPOS ? c : nx - 1 - c)) * 16;
                     if constexpr (K == 1) {
-                        *po = (uint16_t)bf16_bits(w[0] * psi[0]);
+                        *po = __builtin_bit_cast(uint16_t, (__bf16)(w[0] * psi[0]));
                     } else {
                         uint32_t pk[K / 2];
 #pragma unroll
-                        for (int k = 0; k < K; k += 2)
-                            pk[k / 2] = bf16_bits(w[k] * psi[k]) | (bf16_bits(w[k + 1] * psi[k + 1]) << 16);
+                        for (int k = 0; k < K; k += 2) pk[k / 2] = bf16_pack(w[k] * psi[k], w[k + 1] * psi[k + 1]);
                         if constexpr (K == 2) *reinterpret_cast<uint32_t*>(po) = pk[0];
                         else *reinterpret_cast<uint2*>(po) = make_uint2(pk[0], pk[1]);
                     }

@@ -196,11 +196,13 @@ hipError_t launch_init_state(const SystemDev* sys, const ProblemDev* probs, int 
                              hipStream_t s);
 hipError_t launch_moments(const MomentsArgs& a, bool fp64, hipStream_t s);
 hipError_t launch_finish_var(const double* m2, double* var, int64_t cells, int64_t t, hipStream_t s);
-hipError_t launch_contract(const ContractArgs& a, int kind, hipStream_t s);  // 0 bf16 MFMA, 1 fp32, 2 fp64
+// kind 0 bf16 MFMA, 1 fp32, 2 fp64; ctl (may be NULL): the last block stamps ctl->t_mark
+hipError_t launch_contract(const ContractArgs& a, int kind, hipStream_t s, Ctl* ctl = nullptr);
 // Blocks of one contraction (-1: shape not supported by the kind); several contractions in one
 // launch: items [n] on the device, map [nblocks] = (item, block of that item).
 int contract_blocks(const ContractArgs& a, int kind);
-hipError_t launch_contract_batch(const ContractArgs* items, const int2* map, int nblocks, int kind, hipStream_t s);
+hipError_t launch_contract_batch(const ContractArgs* items, const int2* map, int nblocks, int kind, hipStream_t s,
+                                 Ctl* ctl = nullptr);
 hipError_t launch_cast_bf16(const float* in, void* out, int64_t n, hipStream_t s);
 // Kernel matrices of every system of a plan (row sums first when a system is normalized).
 hipError_t launch_kernel_matrix(const KmArgs& a, hipStream_t s);

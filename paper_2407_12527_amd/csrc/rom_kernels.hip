@@ -481,6 +481,7 @@ __device__ __forceinline__ void reset_ctl(Ctl* ctl, int nsys)
     ctl->t_mark = wall_clock64();
     ctl->ticket = 0;
     ctl->blocks_done = 0;
+    ctl->cblocks_done = 0;
     ctl->epoch += 1;
 }
 
@@ -659,18 +660,33 @@ __device__ __forceinline__ void contract_bf16_tile(const ContractArgs& A, const 
     }
 }
 
-__global__ __launch_bounds__(256) void contract_bf16_kernel(ContractArgs A)
+// The contraction is the kernel that precedes the sweep of an anisotropic iteration: the last of
+// its blocks to finish stamps t_mark, from which the sweep is timed (no marking launch between
+// the two).  Blocks of stopped systems return early and still count.
+__device__ __forceinline__ void stamp_when_last(Ctl* ctl)
+{
+    if (!ctl) return;
+    __syncthreads();
+    if (threadIdx.x == 0 && atomicAdd(&ctl->cblocks_done, 1) == (int)gridDim.x - 1) {
+        ctl->t_mark = wall_clock64();
+        ctl->cblocks_done = 0;
+    }
+}
+
+__global__ __launch_bounds__(256) void contract_bf16_kernel(ContractArgs A, Ctl* ctl)
 {
     contract_bf16_tile(A, blockIdx.x, gridDim.x, true);
+    stamp_when_last(ctl);
 }
 
 // The contractions of several systems in one launch: block b computes tile map[b].y of
 // contraction map[b].x (an ensemble's samples each have their own small kernel matrix).
 __global__ __launch_bounds__(256) void contract_bf16_batch_kernel(const ContractArgs* __restrict__ items,
-                                                                  const int2* __restrict__ map)
+                                                                  const int2* __restrict__ map, Ctl* ctl)
 {
     const int2 m = map[blockIdx.x];
     contract_bf16_tile(items[m.x], m.y, 0, false);
+    stamp_when_last(ctl);
 }
 
 // Plain tiled contraction (FP64 or FP32 operands, same precision out), 16 x 16 threads, 64 x 64
@@ -726,17 +742,19 @@ __device__ __forceinline__ void contract_plain_tile(const ContractArgs& A, const
 }
 
 template <typename T>
-__global__ __launch_bounds__(256) void contract_plain_kernel(ContractArgs A)
+__global__ __launch_bounds__(256) void contract_plain_kernel(ContractArgs A, Ctl* ctl)
 {
     contract_plain_tile<T>(A, blockIdx.x);
+    stamp_when_last(ctl);
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void contract_plain_batch_kernel(const ContractArgs* __restrict__ items,
-                                                                   const int2* __restrict__ map)
+                                                                   const int2* __restrict__ map, Ctl* ctl)
 {
     const int2 m = map[blockIdx.x];
     contract_plain_tile<T>(items[m.x], m.y);
+    stamp_when_last(ctl);
 }
 
 // FP32 angular flux -> BF16 copy (used when the sweep stored FP32 psi').
@@ -1037,18 +1055,18 @@ hipError_t launch_finish_var(const double* m2, double* var, int64_t cells, int64
     return hipGetLastError();
 }
 
-hipError_t launch_contract(const ContractArgs& a, int kind, hipStream_t s)
+hipError_t launch_contract(const ContractArgs& a, int kind, hipStream_t s, Ctl* ctl)
 {
     if (kind == 0) {
         if (a.N % GN != 0 || a.K % GK != 0) return hipErrorInvalidValue;
         const int grid = ((a.M + GM - 1) / GM) * (a.N / GN);
-        hipLaunchKernelGGL(contract_bf16_kernel, dim3(grid), dim3(256), 0, s, a);
+        hipLaunchKernelGGL(contract_bf16_kernel, dim3(grid), dim3(256), 0, s, a, ctl);
     } else {
         const int grid = ((a.M + 63) / 64) * ((a.N + 63) / 64);
         if (kind == 1)
-            hipLaunchKernelGGL(contract_plain_kernel<float>, dim3(grid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(contract_plain_kernel<float>, dim3(grid), dim3(256), 0, s, a, ctl);
         else
-            hipLaunchKernelGGL(contract_plain_kernel<double>, dim3(grid), dim3(256), 0, s, a);
+            hipLaunchKernelGGL(contract_plain_kernel<double>, dim3(grid), dim3(256), 0, s, a, ctl);
     }
     return hipGetLastError();
 }
@@ -1059,12 +1077,13 @@ int contract_blocks(const ContractArgs& a, int kind)
     return ((a.M + 63) / 64) * ((a.N + 63) / 64);
 }
 
-hipError_t launch_contract_batch(const ContractArgs* items, const int2* map, int nblocks, int kind, hipStream_t s)
+hipError_t launch_contract_batch(const ContractArgs* items, const int2* map, int nblocks, int kind, hipStream_t s,
+                                 Ctl* ctl)
 {
     if (nblocks < 1) return hipErrorInvalidValue;
-    if (kind == 0) hipLaunchKernelGGL(contract_bf16_batch_kernel, dim3(nblocks), dim3(256), 0, s, items, map);
-    else if (kind == 1) hipLaunchKernelGGL(contract_plain_batch_kernel<float>, dim3(nblocks), dim3(256), 0, s, items, map);
-    else hipLaunchKernelGGL(contract_plain_batch_kernel<double>, dim3(nblocks), dim3(256), 0, s, items, map);
+    if (kind == 0) hipLaunchKernelGGL(contract_bf16_batch_kernel, dim3(nblocks), dim3(256), 0, s, items, map, ctl);
+    else if (kind == 1) hipLaunchKernelGGL(contract_plain_batch_kernel<float>, dim3(nblocks), dim3(256), 0, s, items, map, ctl);
+    else hipLaunchKernelGGL(contract_plain_batch_kernel<double>, dim3(nblocks), dim3(256), 0, s, items, map, ctl);
     return hipGetLastError();
 }
 
