@@ -115,11 +115,17 @@ __device__ __forceinline__ void slot_sums(const T (&acc)[U], T (&out)[U / 4])
 // LDS hand-off counters between the wavefronts of a workgroup.  A wave's LDS operations complete
 // in issue order and LDS is one coherent memory per CU, so publishing needs only the wave's own
 // LDS traffic drained (s_waitcnt lgkmcnt(0)) -- not its global loads and stores, which a
-// memory-model release at workgroup scope would also wait for.
+// memory-model release at workgroup scope would also wait for.  The counters are accessed through
+// LDS-typed pointers: a volatile access through a generic pointer stays a FLAT access (address
+// spaces are not inferred for volatile accesses), and every FLAT load is followed by a wait on
+// the vector-memory counter as well, which drained the wave's prefetched field and source loads
+// and its stores at every poll.
+typedef __attribute__((address_space(3))) int lds_int_t;
+
 __device__ __forceinline__ void lds_publish(int* p, int v)
 {
     asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
-    *(volatile int*)p = v;
+    *(volatile lds_int_t*)p = v;
 }
 
 // Bounded wait on an LDS counter; returns the value seen (cached by the caller).  Reads that
@@ -127,11 +133,11 @@ __device__ __forceinline__ void lds_publish(int* p, int v)
 // wait_gave_up states; a wait that gave up returns the target.
 __device__ __forceinline__ int lds_wait_get(int* p, int target, Ctl* ctl, int limit, long long ticks)
 {
-    int v = *(volatile int*)p;
+    int v = *(volatile lds_int_t*)p;
     if (v < target) {
         const unsigned long long t0 = wall_clock64();
         int spins = 0;
-        while ((v = *(volatile int*)p) < target) {
+        while ((v = *(volatile lds_int_t*)p) < target) {
             __builtin_amdgcn_s_sleep(1);
             if (wait_gave_up(++spins, t0, ctl, limit, ticks)) {
                 v = target;
@@ -373,6 +379,7 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
         }
     };
     const int tsteps = nx + R - 1;                          // steps with a cell in the block
+    const int tlast = (tsteps - 1) / U * U;                 // the last run with a cell
     const int tend = R + U * ((nx + U - 1) / U);            // ... and until the last column is exported
 #pragma unroll
     for (int q = 0; q < PD; ++q)
@@ -550,7 +557,11 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
 #pragma unroll
                     for (int u = 0; u < U; ++u) cS[u] = pS[q][u];
                 }
-                if (tq + PD * U < tsteps) fetch(pst[q], pS[q], pA[q], tq + PD * U);
+                // Refill unconditionally (past the last run, the last run again): with the same
+                // loads on every path the new values take the registers of the ones just copied
+                // out, instead of being moved at the loop latch, a move that must first wait for
+                // every load and store in flight.
+                fetch(pst[q], pS[q], pA[q], min(tq + PD * U, tlast));
                 block(tq, cst, cS, cA);
             }
         }
