@@ -77,14 +77,11 @@ KERNEL_SOURCES = {
               "rom_sweep_f32_8x4.hip", "rom_sweep_f32_8x8.hip", "rom_sweep_f64.hip"],
 }
 MEASURED_TRAFFIC = {  # workload: [(kernel family, shape as in config, source hash, bytes per launch), ...]
-    "c2": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 1, "waves_per_group": 4}, "e1f013e8ca59fc4f", 25516675),
-           ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "e1f013e8ca59fc4f", 38900795),
-           ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 2}, "e1f013e8ca59fc4f", 40638020)],
-    "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "e1f013e8ca59fc4f", 1810208),
-           ("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 1}, "e1f013e8ca59fc4f", 1825374)],
-    "c3": [("strip", {"sweep_tile": "16x16", "band": 4}, "18d77716fe5ec93c", 938536546)],
-    "c4": [("strip", {"sweep_tile": "8x4", "band": 4}, "18d77716fe5ec93c", 446640762)],
-    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "18d77716fe5ec93c", 2737417550)],
+    "c2": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "a5cceaf538db36f6", 38920000)],
+    "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "a5cceaf538db36f6", 1700000)],
+    "c3": [("strip", {"sweep_tile": "16x16", "band": 4}, "9d805dc2986534da", 933670000)],
+    "c4": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 4, "waves_per_group": 4}, "a5cceaf538db36f6", 470970000)],
+    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "9d805dc2986534da", 3179380000)],
 }
 
 
