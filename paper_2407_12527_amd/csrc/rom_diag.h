@@ -368,11 +368,19 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
         const int64_t c0 = lane0 + (int64_t)DIR * t0;
         load_row_run<T, U, DIR>(D.st, c0, fst);
         if constexpr (ANG) {
+            if (t0 >= R && t0 + U <= nx) {
+                // every lane's cells of these steps lie inside its row: one address, the steps at
+                // fixed offsets from it
+                const float* const p = ang_lane + (rowbase + (XPOS ? t0 - r : nx - 1 - t0 + r)) * 16;
 #pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int c = min(max(t0 + u - r, 0), nx - 1);
-                const int64_t cell = rowbase + (XPOS ? c : nx - 1 - c);
-                fA[u] = *reinterpret_cast<const VK*>(ang_lane + cell * 16);
+                for (int u = 0; u < U; ++u) fA[u] = *reinterpret_cast<const VK*>(p + DIR * u * 16);
+            } else {
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    const int c = min(max(t0 + u - r, 0), nx - 1);
+                    const int64_t cell = rowbase + (XPOS ? c : nx - 1 - c);
+                    fA[u] = *reinterpret_cast<const VK*>(ang_lane + cell * 16);
+                }
             }
         } else {
             load_row_run<T, U, DIR>(D.S, c0, fS);
@@ -422,6 +430,7 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
             if (need > 0 && seen_out < need) seen_out = lds_wait_get(&cons[wave], need, A.ctl, A.spin_limit, A.wait_ticks);
         }
 
+        uint16_t* const psi_blk = ANG ? D.psi + obase + (rowbase + (XPOS ? t0 - r : nx - 1 - t0 + r)) * 16 : nullptr;
         // MODE 0: every lane inside its row; 1: lanes before their row start hold their x-face
         // inflow; 2: lanes outside their row store nothing
         T acc[U];
@@ -442,10 +451,12 @@ __device__ __forceinline__ void diag_block(const DiagArgs& A, const DiagTask<T>&
                 hist[k][u] = psi[k];
                 acc[u] = k == 0 ? w[k] * v : fma(w[k], v, acc[u]);
             }
-            // dense kernels: the cell's weighted angular flux, K BF16 values per lane
+            // dense kernels: the cell's weighted angular flux, K BF16 values per lane (inside the
+            // rows, MODE 0, at fixed offsets from the block's address)
             if constexpr (ANG) {
-                if (row_ok && c >= 0 && c < nx) {
-                    uint16_t* const po = D.psi + obase + (rowbase + (XPOS ? c : nx - 1 - c)) * 16;
+                if (row_ok && (MODE == 0 || (c >= 0 && c < nx))) {
+                    uint16_t* const po = MODE == 0 ? psi_blk + DIR * u * 16
+                                                   : D.psi + obase + (rowbase + (XPOS ? c : nx - 1 - c)) * 16;
                     if constexpr (K == 1) {
                         *po = __builtin_bit_cast(uint16_t, (__bf16)(w[0] * psi[0]));
                     } else {

@@ -662,10 +662,11 @@ __device__ __forceinline__ void contract_bf16_tile(const ContractArgs& A, const 
 
 // The contraction is the kernel that precedes the sweep of an anisotropic iteration: the last of
 // its blocks to finish stamps t_mark, from which the sweep is timed (no marking launch between
-// the two).  Blocks of stopped systems return early and still count.
+// the two).  Blocks of stopped systems return early and still count; once every system has
+// stopped (replays past convergence) nothing is stamped and no block touches the counter.
 __device__ __forceinline__ void stamp_when_last(Ctl* ctl)
 {
-    if (!ctl) return;
+    if (!ctl || ctl->active == 0) return;  // written by the combine step before this launch
     __syncthreads();
     if (threadIdx.x == 0 && atomicAdd(&ctl->cblocks_done, 1) == (int)gridDim.x - 1) {
         ctl->t_mark = wall_clock64();
@@ -675,6 +676,7 @@ __device__ __forceinline__ void stamp_when_last(Ctl* ctl)
 
 __global__ __launch_bounds__(256) void contract_bf16_kernel(ContractArgs A, Ctl* ctl)
 {
+    if (ctl && ctl->active == 0) return;  // every system has stopped
     contract_bf16_tile(A, blockIdx.x, gridDim.x, true);
     stamp_when_last(ctl);
 }
@@ -684,6 +686,7 @@ __global__ __launch_bounds__(256) void contract_bf16_kernel(ContractArgs A, Ctl*
 __global__ __launch_bounds__(256) void contract_bf16_batch_kernel(const ContractArgs* __restrict__ items,
                                                                   const int2* __restrict__ map, Ctl* ctl)
 {
+    if (ctl && ctl->active == 0) return;  // every system has stopped
     const int2 m = map[blockIdx.x];
     contract_bf16_tile(items[m.x], m.y, 0, false);
     stamp_when_last(ctl);
@@ -744,6 +747,7 @@ __device__ __forceinline__ void contract_plain_tile(const ContractArgs& A, const
 template <typename T>
 __global__ __launch_bounds__(256) void contract_plain_kernel(ContractArgs A, Ctl* ctl)
 {
+    if (ctl && ctl->active == 0) return;  // every system has stopped
     contract_plain_tile<T>(A, blockIdx.x);
     stamp_when_last(ctl);
 }
@@ -752,6 +756,7 @@ template <typename T>
 __global__ __launch_bounds__(256) void contract_plain_batch_kernel(const ContractArgs* __restrict__ items,
                                                                    const int2* __restrict__ map, Ctl* ctl)
 {
+    if (ctl && ctl->active == 0) return;  // every system has stopped
     const int2 m = map[blockIdx.x];
     contract_plain_tile<T>(items[m.x], m.y);
     stamp_when_last(ctl);
