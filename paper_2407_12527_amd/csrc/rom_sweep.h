@@ -161,14 +161,15 @@ __device__ __forceinline__ void store_partials(const RowCtx& R, double (&acc)[TX
 #endif
 
 // Waves per SIMD the compiler must leave room for.  The FP32 isotropic flux-only step sweeps fit
-// four waves in 128 VGPRs without spilling (tiles of up to 128 cells, and 16 x 16 with 64-lane
-// groups); the extra wave hides the LDS and hand-off waits of the row loop (c5 sweep 58.3 ->
-// 53.9 ms per solve).  Every other variant would spill at that bound and keeps the compiler's
+// four waves in 128 VGPRs (tiles of up to 128 cells, and 16 x 16 with 64-lane groups without
+// spilling; 16 x 16 with 32-lane groups spills 32 bytes outside the row loop); the extra wave
+// hides the LDS and hand-off waits of the row loop (c5 sweep 58.3 -> 53.9 ms per solve, c3 sweep
+// 950 -> 935 us).  Every other variant would spill more at that bound and keeps the compiler's
 // own register budget.
 template <typename T, int TX, int TY, bool DD, bool ANG, int PSI, int L, int MOM>
 constexpr int sweep_waves_per_simd()
 {
-    return (sizeof(T) == 4 && !DD && !ANG && PSI == 0 && MOM == 1 && (TX * TY <= 128 || L == 64)) ? 4 : 1;
+    return (sizeof(T) == 4 && !DD && !ANG && PSI == 0 && MOM == 1 && (TX * TY <= 128 || L >= 32)) ? 4 : 1;
 }
 
 template <typename T, int TX, int TY, bool DD, bool ANG, int PSI, int L, int MOM>
