@@ -193,7 +193,9 @@ int rom_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_fn)(v
 
 /* Set the ordinate set: dirs [n][3] (c, s, zeta) with c^2 + s^2 + zeta^2 = 1 (to 1e-12) and
  * weights w [n] summing to 1 (to 1e-12), as DOM requires after the Sec. 2 system.  Ordinates are
- * regrouped by quadrant on the device; outputs keep the caller's order. */
+ * regrouped by quadrant on the device; outputs keep the caller's order.  A dense kernel set
+ * before (ROM_SCAT_DENSE) is indexed by the old set: solves return ROM_E_STATE until it is set
+ * again. */
 int rom_set_ordinates(rom_handle* h, int32_t n, const double* dirs, const double* w);
 
 /* Angular inflow psi_Gamma(z, u_l) on one face (eq. (3.2)): vals is [n][ny] (left/right) or

@@ -1594,6 +1594,9 @@ std::string plan_signature(const rom_si_opts& o, int sig, int kind, int nsys)
     return buf;
 }
 
+// A dense kernel whose ordinate set has since been replaced (rom_set_ordinates clears it).
+bool dense_stale(const rom_handle* h) { return h->scat == ROM_SCAT_DENSE && h->Pdense.size() != (size_t)h->n * h->n; }
+
 int check_ordinates(rom_handle* h, int n, const double* dirs, const double* w)
 {
     if (n <= 0 || !dirs || !w) return fail(h, ROM_E_ARG, "ordinates: n must be > 0 and arrays non-NULL");
@@ -1731,11 +1734,7 @@ int rom_set_ordinates(rom_handle* h, int32_t n, const double* dirs, const double
     h->dirs.assign(dirs, dirs + 3 * (size_t)n);
     h->w.assign(w, w + n);
     for (auto& a : h->ang) a.clear();
-    if (h->scat == ROM_SCAT_DENSE) {
-        h->scat = ROM_SCAT_ISO;
-        h->scat_norm = false;
-        h->Pdense.clear();
-    }
+    h->Pdense.clear();  // a dense kernel is indexed by the old set: solves refuse until it is set again
     h->version++;
     return ROM_OK;
 }
@@ -2238,6 +2237,7 @@ int rom_source_iterate(rom_handle* h, const rom_si_opts* opts, double* phi, rom_
     ROM_API_LOCK;
     if (!h) return ROM_E_ARG;
     if (h->n == 0) return fail(h, ROM_E_STATE, "set ordinates first");
+    if (dense_stale(h)) return fail(h, ROM_E_STATE, "the dense kernel was set for another ordinate set: set it again");
     rom_si_opts o;
     int rc = validate_opts(h, opts, o);
     if (rc) return rc;
@@ -2291,6 +2291,7 @@ int rom_solve_batch(rom_handle* const* hs, int32_t k, const rom_si_opts* opts, d
     for (int i = 0; i < k; ++i) {
         if (!hs[i]) return fail(h0, ROM_E_ARG, "NULL handle in batch");
         if (hs[i]->n == 0) return fail(h0, ROM_E_STATE, "every handle needs ordinates");
+        if (dense_stale(hs[i])) return fail(h0, ROM_E_STATE, "a dense kernel was set for another ordinate set: set it again");
         if (hs[i]->user_stream != h0->user_stream) return fail(h0, ROM_E_ARG, "handles must share one stream");
         if (hs[i]->scat == ROM_SCAT_DENSE && k > 1) return fail(h0, ROM_E_UNSUPPORTED, "dense kernels are not batched");
         for (int j = 0; j < i; ++j)

@@ -160,6 +160,13 @@ def test_handle_validation_without_device(R):
         Z = np.array([[0.0, 0.0], [0.2, 1.0]])
         assert R.rom_set_scattering(h, R.ROM_SCAT_DENSE | R.ROM_SCAT_NORMALIZE, 0.0, Z.ctypes.data) == R.ROM_E_DOMAIN
         assert R.rom_set_scattering(h, R.ROM_SCAT_DENSE, 0.0, Z.ctypes.data) == 0
+        # new ordinates leave the dense kernel indexed by the old set: solves refuse until it is
+        # set again (even for the same count), and a fresh kernel clears the refusal
+        assert R.rom_set_ordinates(h, 2, d.ctypes.data, w.ctypes.data) == 0
+        assert R.rom_source_iterate(h, None, None, None) == R.ROM_E_STATE
+        hs = (C.c_void_p * 1)(h.value)
+        assert R.rom_solve_batch(hs, 1, None, None, None) == R.ROM_E_STATE
+        assert R.rom_set_scattering(h, R.ROM_SCAT_DENSE, 0.0, Z.ctypes.data) == 0
         assert R.rom_set_scattering(h, R.ROM_SCAT_HG, 0.8, None) == 0
         ang = -np.ones(2 * 3)
         assert R.rom_set_inflow_angular(h, R.ROM_FACE_LEFT, ang.ctypes.data) == R.ROM_E_DOMAIN
