@@ -62,7 +62,7 @@ BYTES_PER_ANG_UPDATE = 6.0
 PINNED = {
     "c1": {"sweep": "diag", "diag_rows": 64, "diag_k": 1, "band": 2, "tile": "0x0"},
     "c2": {"sweep": "diag", "diag_rows": 64, "diag_k": 2, "band": 4, "tile": "0x0"},
-    "c3": {"sweep": "strip", "tile": "16x16", "band": 8, "diag_rows": 0, "diag_k": 0},
+    "c3": {"sweep": "strip", "tile": "16x16", "band": 7, "diag_rows": 0, "diag_k": 0},
     "c4": {"sweep": "diag", "diag_rows": 16, "diag_k": 4, "band": 4, "tile": "0x0"},
     "c5": {"sweep": "strip", "tile": "16x16", "band": 4, "diag_rows": 0, "diag_k": 0},
 }
@@ -80,7 +80,7 @@ KERNEL_SOURCES = {
 MEASURED_TRAFFIC = {  # workload: [(kernel family, shape as in config, source hash, bytes per launch), ...]
     "c2": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "a5cceaf538db36f6", 38920000)],
     "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "a5cceaf538db36f6", 1700000)],
-    "c3": [("strip", {"sweep_tile": "16x16", "band": 8}, "c223a105963b996a", 725720000)],
+    "c3": [("strip", {"sweep_tile": "16x16", "band": 7}, "c223a105963b996a", 838270000)],
     "c4": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 4, "waves_per_group": 4}, "a5cceaf538db36f6", 470970000)],
     "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "c223a105963b996a", 3179190000)],
 }
