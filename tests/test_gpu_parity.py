@@ -130,6 +130,29 @@ def test_sweep_degenerate_grids(R, orc, shape):
     parity.check(phi, orc.scalar_flux(w, orc.sweep(p, d, S)), 1e-13)
 
 
+@pytest.mark.parametrize("kernel", ["strip", "row-lane"])
+@pytest.mark.parametrize("shape", [(1500, 2), (2, 1500), (700, 41)])
+def test_sweep_elongated_grids(R, orc, kernel, shape):
+    """Long strips and tall stacks: hundreds of chunks per strip, or hundreds of strips (8 x 4
+    tiles in bands of 2, so most strip boundaries go through global memory) and of 16-row blocks,
+    with inflow on all four faces; FP64, so the result is the oracle's to rounding."""
+    nx, ny = shape
+    rng = np.random.default_rng(nx + 7 * ny)
+    st, ss, q = rand_problem(rng, nx, ny)
+    inflow = {"left": rng.uniform(0, 1, ny), "right": rng.uniform(0, 1, ny), "bottom": rng.uniform(0, 1, nx),
+              "top": rng.uniform(0, 1, nx)}
+    h, p = both(R, orc, nx, ny, st, ss, q, box=(0.0, 2.0, 0.0, 1.0), inflow=inflow)
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 2, 3, seed=3)
+    h.set_ordinates(d, w)
+    S = rng.uniform(0, 1, nx * ny)
+    if kernel == "strip":
+        o = R.si_opts(precision=R.ROM_PREC_FP64, sweep=R.ROM_SWEEP_STRIP, tile=(8, 4), band=2)
+    else:
+        o = R.si_opts(precision=R.ROM_PREC_FP64, sweep=R.ROM_SWEEP_DIAG, diag_rows=16, diag_k=1, band=4)
+    phi = h.sweep(S, o)
+    parity.check(phi, orc.scalar_flux(w, orc.sweep(p, d, S)), 1e-12)
+
+
 def test_single_ordinate(R, orc):
     nx, ny = 9, 7
     st, ss, q = np.ones(63), np.full(63, 0.3), np.ones(63)
