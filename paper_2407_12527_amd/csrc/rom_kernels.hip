@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 #include <stdint.h>
+#include <cstdlib>
 
 #include "rom_common.h"
 
@@ -692,6 +693,136 @@ __global__ __launch_bounds__(256) void contract_bf16_batch_kernel(const Contract
     stamp_when_last(ctl);
 }
 
+// Large single contractions (N >= 256): 512 threads = 8 waves in a 2 x 4 arrangement, block tile
+// 256 x 256, each wave 128 x 64 = 4 x 2 tiles of v_mfma_f32_32x32x16_bf16.  The larger tile
+// halves the operand traffic from L2 per flop against 128 x 128 (every A row-block is read N / 256
+// times, every B row-block M / 256 times).  K steps of 64 go through two LDS buffers: at the top of
+// step k the registers holding step k + 1 are written to the other buffer (read during step k - 1,
+// released by that step's barrier) and the loads of step k + 2 are issued, so the global loads
+// have a whole step of matrix work to land and each step needs one barrier.  146 KiB of LDS: one
+// workgroup per CU, two waves per SIMD.  N may end in a half tile of 128 columns: the waves whose
+// columns lie past N skip the matrix work and the stores.
+constexpr int BM2 = 256, BN2 = 256;
+constexpr int kRowStep2 = 512 / kSegs;     // tile rows moved by the block per piece (64)
+constexpr int kStage2 = BM2 / kRowStep2;   // 16-byte pieces of one operand tile per thread (4)
+constexpr size_t kBigLds = 2 * 2 * (size_t)BM2 * (GK + LDS_PAD) * sizeof(__bf16) + 2 * BM2 * sizeof(float);
+
+__global__ __launch_bounds__(512) void contract_bf16_big_kernel(ContractArgs A, Ctl* ctl)
+{
+    if (ctl && ctl->active == 0) return;  // every system has stopped
+    if (A.sysctl && A.sysctl[A.sys_index].state != 0) {
+        stamp_when_last(ctl);
+        return;
+    }
+    extern __shared__ __attribute__((aligned(16))) unsigned char big_smem[];
+    typedef __bf16 Row[GK + LDS_PAD];
+    Row* As = (Row*)big_smem;                  // [2][BM2] rows
+    Row* Bs = As + 2 * BM2;                    // [2][BN2] rows
+    float* ss_q = (float*)(Bs + 2 * BN2);      // [2][BM2]: sigma_s, q
+    const int tid = threadIdx.x;
+    const int wave = tid / 64, lane = tid % 64;
+    const int wm = wave / 4, wn = wave % 4;
+    const int nb = gridDim.x, blk = blockIdx.x;
+    const int nblk_n = (A.N + BN2 - 1) / BN2;
+    // XCD-aware order, as in the 128 x 128 kernel: the N tiles of one A row-block on one XCD
+    const int lb = (nb % 8 == 0) ? (blk % 8) * (nb / 8) + blk / 8 : blk;
+    const int bm = lb / nblk_n, bn = lb % nblk_n;
+    const int m0 = bm * BM2, n0 = bn * BN2;
+    const bool live = n0 + wn * 64 < A.N;  // uniform per wave
+    const __bf16* __restrict__ Ag = (const __bf16*)A.a;
+    const __bf16* __restrict__ Bg = (const __bf16*)A.bt;
+    if (tid < 2 * BM2) {
+        const int r = min(m0 + tid % BM2, A.M - 1);
+        ss_q[tid] = tid < BM2 ? ((const float*)A.sigma_s)[r] : ((const float*)A.q)[r];
+    }
+
+    f32x16_t acc[4][2];
+#pragma unroll
+    for (int x = 0; x < 4; ++x)
+#pragma unroll
+        for (int y = 0; y < 2; ++y)
+#pragma unroll
+            for (int e = 0; e < 16; ++e) acc[x][y][e] = 0.0f;
+
+    typedef unsigned u32x4 __attribute__((ext_vector_type(4)));
+    u32x4 ra[kStage2], rb[kStage2];
+    const int row0 = tid / kSegs, seg = tid % kSegs;
+    const bool blocked = A.blocked != 0;
+    // rows past M (A) or N (B) read the last row (in bounds); their results are never stored
+    auto a_at = [&](const int h) {
+        const int64_t m = min(m0 + row0 + kRowStep2 * h, A.M - 1);
+        return blocked ? Ag + ((int64_t)(seg / 2) * A.M + m) * 16 + (seg % 2) * 8 : Ag + m * A.K + seg * 8;
+    };
+    const int64_t a_kstep = blocked ? (int64_t)(GK / 16) * A.M * 16 : GK;
+    auto b_at = [&](const int h) {
+        const int64_t n = min(n0 + row0 + kRowStep2 * h, A.N - 1);
+        return Bg + n * A.K + seg * 8;
+    };
+    auto load = [&](const int ks) {
+#pragma unroll
+        for (int h = 0; h < kStage2; ++h) {
+            ra[h] = *(const u32x4*)(a_at(h) + ks * a_kstep);
+            rb[h] = *(const u32x4*)(b_at(h) + ks * GK);
+        }
+    };
+    auto stage = [&](const int buf) {
+#pragma unroll
+        for (int h = 0; h < kStage2; ++h) {
+            *(u32x4*)&As[buf * BM2 + row0 + kRowStep2 * h][seg * 8] = ra[h];
+            *(u32x4*)&Bs[buf * BN2 + row0 + kRowStep2 * h][seg * 8] = rb[h];
+        }
+    };
+    const int nk = A.K / GK;
+    load(0);
+    stage(0);
+    if (nk > 1) load(1);
+    __syncthreads();
+    for (int ks = 0; ks < nk; ++ks) {
+        const int cur = ks & 1;
+        if (ks + 1 < nk) {
+            stage(cur ^ 1);
+            if (ks + 2 < nk) load(ks + 2);
+        }
+        if (live) {
+#pragma unroll
+            for (int kk = 0; kk < GK; kk += 16) {
+                bf16x8_t af[4], bfr[2];
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+                    af[x] = *(const bf16x8_t*)&As[cur * BM2 + wm * 128 + x * 32 + (lane % 32)][kk + 8 * (lane / 32)];
+#pragma unroll
+                for (int y = 0; y < 2; ++y)
+                    bfr[y] = *(const bf16x8_t*)&Bs[cur * BN2 + wn * 64 + y * 32 + (lane % 32)][kk + 8 * (lane / 32)];
+#pragma unroll
+                for (int x = 0; x < 4; ++x)
+#pragma unroll
+                    for (int y = 0; y < 2; ++y)
+                        acc[x][y] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[x], bfr[y], acc[x][y], 0, 0, 0);
+            }
+        }
+        __syncthreads();
+    }
+    // epilogue: lane holds column (lane % 32) and rows 8*(e/4) + 4*(lane/32) + e%4 of each tile
+    if (live) {
+        float* __restrict__ out = (float*)A.out;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int col = n0 + wn * 64 + y * 32 + (lane % 32);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int rl = wm * 128 + x * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+                    const int row = m0 + rl;
+                    const int64_t at = blocked ? ((int64_t)(col / 16) * A.M + row) * 16 + col % 16 : (int64_t)row * A.N + col;
+                    if (row < A.M) out[at] = fmaf(ss_q[rl], acc[x][y][e], ss_q[BM2 + rl]);
+                }
+            }
+        }
+    }
+    stamp_when_last(ctl);
+}
+
 // Plain tiled contraction (FP64 or FP32 operands, same precision out), 16 x 16 threads, 64 x 64
 // block tile, each thread a 4 x 4 micro-tile.
 template <typename T>
@@ -1060,10 +1191,28 @@ hipError_t launch_finish_var(const double* m2, double* var, int64_t cells, int64
     return hipGetLastError();
 }
 
+// 256 x 256 tiles for large single contractions unless ROM_CONTRACT_TILE=128 (timing comparisons).
+static bool contract_big_tiles()
+{
+    static const bool big = [] {
+        const char* e = std::getenv("ROM_CONTRACT_TILE");
+        return !(e && std::atoi(e) == 128);
+    }();
+    return big;
+}
+
 hipError_t launch_contract(const ContractArgs& a, int kind, hipStream_t s, Ctl* ctl)
 {
     if (kind == 0) {
         if (a.N % GN != 0 || a.K % GK != 0) return hipErrorInvalidValue;
+        if (a.N >= 2 * GN && contract_big_tiles()) {
+            const hipError_t e = hipFuncSetAttribute((const void*)contract_bf16_big_kernel,
+                                                     hipFuncAttributeMaxDynamicSharedMemorySize, (int)kBigLds);
+            if (e != hipSuccess) return e;
+            const int grid = ((a.M + BM2 - 1) / BM2) * ((a.N + BN2 - 1) / BN2);
+            hipLaunchKernelGGL(contract_bf16_big_kernel, dim3(grid), dim3(512), kBigLds, s, a, ctl);
+            return hipGetLastError();
+        }
         const int grid = ((a.M + GM - 1) / GM) * (a.N / GN);
         hipLaunchKernelGGL(contract_bf16_kernel, dim3(grid), dim3(256), 0, s, a, ctl);
     } else {

@@ -260,6 +260,28 @@ def test_si_anisotropic_hg(R, orc, prec):
     parity.si_check(orc, p, d, w, W, phi, st.iters, 1e-7, 1e-9 if prec == "fp64" else 2e-3)
 
 
+@pytest.mark.parametrize("shape", [(23, 17, 16, 4), (37, 29, 64, 1)])
+def test_si_anisotropic_large_contraction_ragged(R, orc, shape):
+    """320 ordinates (80 per quadrant) on the row-lane dense path pad to 384 kernel columns: the
+    256 x 256 contraction tiles end in a half tile of 128 columns, and the cell count (391, 1073)
+    leaves a ragged last row tile.  Three fixed iterations against the oracle at the BF16 bar."""
+    nx, ny, rows, k = shape
+    rng = np.random.default_rng(nx * ny)
+    st, ss, q = rand_problem(rng, nx, ny, 0.8)
+    h, p = both(R, orc, nx, ny, st, ss, q, inflow={"left": rng.uniform(0, 1, ny)})
+    d, w = R.generate_ordinates(R.ROM_ORD_STRATIFIED, 8, 10, seed=4)
+    assert d.shape[0] == 320
+    h.set_ordinates(d, w)
+    h.set_scattering(R.ROM_SCAT_HG, 0.6)
+    W = orc.build_W(d, w, orc.SCAT_HG, 0.6, fold=1)
+    o = R.si_opts(tol=-1.0, max_iter=3, precision=R.ROM_PREC_FP32, sweep=R.ROM_SWEEP_DIAG, diag_rows=rows,
+                  diag_k=k, band=4)
+    phi, stt, rc = h.source_iterate(o)
+    assert rc == R.ROM_NOT_CONVERGED and stt.iters == 3
+    ref = orc.source_iterate(p, d, w, W, tol=0.0, max_iter=3)
+    parity.check(phi, ref["phi"], 2e-3)
+
+
 def test_si_anisotropic_dense_fixed_iterations_fp64(R, orc):
     """A non-symmetric caller kernel with unequal weights (Gaussian set): pins the orientation of
     the contraction on the GPU at a fixed iteration count."""
