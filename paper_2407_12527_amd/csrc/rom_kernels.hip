@@ -545,6 +545,7 @@ __global__ void finish_var_kernel(const double* m2, double* var, int64_t cells, 
 // the global-load latency overlaps the MFMA of the step before it.
 typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 
 constexpr int GM = 128, GN = 128, GK = 64;
 constexpr int LDS_PAD = 8;  // bf16 elements of padding per LDS row (keeps 16-byte alignment)
@@ -803,7 +804,38 @@ __global__ __launch_bounds__(512) void contract_bf16_big_kernel(ContractArgs A, 
         __syncthreads();
     }
     // epilogue: lane holds column (lane % 32) and rows 8*(e/4) + 4*(lane/32) + e%4 of each tile
-    if (live) {
+    if (live && blocked) {
+        // Through LDS (the operand buffers are free after the last barrier): per row tile x, the
+        // wave's 32 x 64 results go to its own slice (4 column blocks of 16; rows padded to 20
+        // floats and blocks to 672 so the 4-byte writes do not conflict), then leave as 16-byte
+        // stores, each instruction one contiguous KB of the blocked output (16 rows of a block).
+        constexpr int RS = 20, CS = 672;
+        float* slice = (float*)big_smem + wave * 4 * CS;
+        float* __restrict__ out = (float*)A.out;
+        const int gcb0 = (n0 + wn * 64) / 16;
+#pragma unroll
+        for (int x = 0; x < 4; ++x) {
+#pragma unroll
+            for (int y = 0; y < 2; ++y) {
+                const int col = y * 32 + (lane % 32);
+#pragma unroll
+                for (int e = 0; e < 16; ++e) {
+                    const int rr = 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
+                    const int rl = wm * 128 + x * 32 + rr;
+                    slice[(col / 16) * CS + rr * RS + col % 16] = fmaf(ss_q[rl], acc[x][y][e], ss_q[BM2 + rl]);
+                }
+            }
+            // a wave's LDS accesses complete in order: the reads below see the writes above, and
+            // the next x's writes come after these reads
+#pragma unroll
+            for (int jb = 0; jb < 8; ++jb) {
+                const int cb = jb / 2, rr = (jb % 2) * 16 + lane / 4, q4 = lane % 4;
+                const f32x4_t v = *(const f32x4_t*)&slice[cb * CS + rr * RS + q4 * 4];
+                const int row = m0 + wm * 128 + x * 32 + rr;
+                if (row < A.M) *(f32x4_t*)&out[((int64_t)(gcb0 + cb) * A.M + row) * 16 + q4 * 4] = v;
+            }
+        }
+    } else if (live) {
         float* __restrict__ out = (float*)A.out;
 #pragma unroll
         for (int x = 0; x < 4; ++x) {
@@ -814,8 +846,7 @@ __global__ __launch_bounds__(512) void contract_bf16_big_kernel(ContractArgs A, 
                 for (int e = 0; e < 16; ++e) {
                     const int rl = wm * 128 + x * 32 + 8 * (e / 4) + 4 * (lane / 32) + (e % 4);
                     const int row = m0 + rl;
-                    const int64_t at = blocked ? ((int64_t)(col / 16) * A.M + row) * 16 + col % 16 : (int64_t)row * A.N + col;
-                    if (row < A.M) out[at] = fmaf(ss_q[rl], acc[x][y][e], ss_q[BM2 + rl]);
+                    if (row < A.M) out[(int64_t)row * A.N + col] = fmaf(ss_q[rl], acc[x][y][e], ss_q[BM2 + rl]);
                 }
             }
         }
