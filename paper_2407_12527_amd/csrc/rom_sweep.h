@@ -156,8 +156,10 @@ __device__ __forceinline__ void store_partials(const RowCtx& R, double (&acc)[TX
 // strips of one wave-stream: wave k sweeps strip band*NW + k.  Edges between strips of a band go
 // through LDS ring buffers (RB chunk slots per boundary, produced / consumed counters in LDS);
 // only the band's top edge goes to global memory for the next band, behind a progress counter.
+// Isotropic flux-only step sweeps reduce each row after the next row has read it (below); 0 takes
+// rows in pairs and reduces each at once (c5 sweep 2751 us against 2660 us deferred, c3 861 / 816).
 #ifndef ROM_SWEEP_DEFER
-#define ROM_SWEEP_DEFER 0
+#define ROM_SWEEP_DEFER 1
 #endif
 
 // Waves per SIMD the compiler must leave room for.  The FP32 isotropic flux-only step sweeps fit
