@@ -78,11 +78,11 @@ KERNEL_SOURCES = {
               "rom_sweep_f32_8x4.hip", "rom_sweep_f32_8x8.hip", "rom_sweep_f64.hip"],
 }
 MEASURED_TRAFFIC = {  # workload: [(kernel family, shape as in config, source hash, bytes per launch), ...]
-    "c2": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "a5cceaf538db36f6", 38920000)],
-    "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "a5cceaf538db36f6", 1700000)],
-    "c3": [("strip", {"sweep_tile": "16x16", "band": 7}, "5553b06b8b071866", 834020000)],
-    "c4": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 4, "waves_per_group": 4}, "a5cceaf538db36f6", 471390000)],
-    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "5553b06b8b071866", 3174950000)],
+    "c2": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "3a383673ce2258ac", 38870000)],
+    "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "3a383673ce2258ac", 1700000)],
+    "c3": [("strip", {"sweep_tile": "16x16", "band": 7}, "05e4cf45e208737f", 846850000)],
+    "c4": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 4, "waves_per_group": 4}, "3a383673ce2258ac", 471680000)],
+    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "05e4cf45e208737f", 3193120000)],
 }
 
 

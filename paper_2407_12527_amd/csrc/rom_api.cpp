@@ -833,9 +833,10 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
         int maxstrips = 1;
         for (auto& si : in) maxstrips = std::max(maxstrips, (si.h->grid.ny + TY - 1) / TY);
         P.band = o.band > 0 ? o.band : std::min(kMaxBand, maxstrips);
-        // when choosing automatically, keep two workgroups per CU (160 KiB of LDS): on a 512^2
-        // problem with 32-lane groups band 7 (71 KiB) measured 871 us per sweep, band 8 (82 KiB,
-        // one workgroup per CU) 908 us and band 6 1008 us
+        // when choosing automatically, keep two workgroups per CU (160 KiB of LDS): longer bands
+        // keep more strip hand-offs in LDS, but a band that leaves one workgroup per CU measured
+        // slower (512^2, 32-lane groups: band 8 at 82 KiB 908 us per sweep against 871 us at
+        // band 7, two ring slots per boundary)
         while (o.band == 0 && P.band > 1 && sweep_lds_bytes(P.fp64, TX, TY, aniso, P.L, P.band, P.nmom) > 80 * 1024) --P.band;
         if (sweep_lds_bytes(P.fp64, TX, TY, aniso, P.L, P.band, P.nmom) > 160 * 1024)
             throw Fail{ROM_E_ARG, "band too large for this tile shape (LDS)"};

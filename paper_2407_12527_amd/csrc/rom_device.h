@@ -25,7 +25,11 @@ namespace rom {
 constexpr int kWave = 64;
 constexpr int kMaxGroups = 4;
 constexpr int kMaxBand = 8;    // wavefronts (consecutive strips) per sweep workgroup
-constexpr int kRingSlots = 2;  // LDS ring slots per strip boundary inside a band
+// LDS ring slots per strip boundary inside a band.  One suffices: the wave above reads chunk c's
+// edge as soon as it is published, a whole chunk before the wave below has its next edge ready
+// (c3 sweep 822 -> 800 us against two slots, c5 2653 -> 2633 us; the smaller LDS lets c3's
+// 8-wave bands keep two workgroups per CU).
+constexpr int kRingSlots = 1;
 
 struct ProblemDev {
     int32_t nx, ny;

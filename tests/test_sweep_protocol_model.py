@@ -37,7 +37,7 @@ class Shape:
     n: int            # ordinates (a multiple of 4: mirrored quadrants)
     lanes: int        # lanes per ordinate group (16, 32, 64)
     wgs: int          # persistent workgroups
-    rb: int = 2       # LDS ring slots per strip boundary
+    rb: int = 1       # LDS ring slots per strip boundary (the library's kRingSlots)
 
 
 @dataclass
@@ -228,11 +228,13 @@ SHAPES = [
     Shape(64, 48, 8, 4, 4, 1024, 64, 1), Shape(64, 48, 8, 4, 4, 1024, 64, 5),
     # ragged strips and chunks, single-wave bands, more bands than workgroups
     Shape(37, 29, 8, 4, 1, 40, 16, 2), Shape(37, 29, 8, 4, 3, 40, 16, 1), Shape(23, 70, 16, 8, 2, 24, 16, 3),
+    # two ring slots per boundary (the protocol allows any count)
+    Shape(40, 40, 8, 4, 4, 128, 32, 2, rb=2), Shape(37, 29, 8, 4, 3, 40, 16, 1, rb=2),
 ]
 
 
 @pytest.mark.parametrize("variant", [False, True], ids=["committed", "reordered"])
-@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s.nx}x{s.ny}_t{s.tx}x{s.ty}_b{s.band}_n{s.n}_L{s.lanes}_w{s.wgs}")
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: f"{s.nx}x{s.ny}_t{s.tx}x{s.ty}_b{s.band}_n{s.n}_L{s.lanes}_w{s.wgs}_rb{s.rb}")
 def test_protocol_is_live_and_safe(shape, variant):
     plan = build_plan(shape)
     for seed in range(6):
@@ -240,7 +242,7 @@ def test_protocol_is_live_and_safe(shape, variant):
         assert not errs, errs[:3]
 
 
-@pytest.mark.parametrize("shape", SHAPES[:6], ids=lambda s: f"{s.nx}x{s.ny}_t{s.tx}x{s.ty}_b{s.band}_n{s.n}_L{s.lanes}_w{s.wgs}")
+@pytest.mark.parametrize("shape", SHAPES[:6], ids=lambda s: f"{s.nx}x{s.ny}_t{s.tx}x{s.ty}_b{s.band}_n{s.n}_L{s.lanes}_w{s.wgs}_rb{s.rb}")
 def test_offset_read_once_stays_in_range_but_is_wrong(shape):
     """Reading the lane's angular offset once per workgroup keeps every address inside the
     pool (the offsets of one system's wave-streams are all below npad): the variant cannot
