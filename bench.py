@@ -57,8 +57,8 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_ISO_UPDATE = 20.0 / 64.0
 BYTES_PER_ANG_UPDATE = 6.0
 
-# The sweep shape each workload's headline is timed with: the fastest of the autotuner's candidates
-# in full-solve timings on MI355X.
+# The sweep shape each workload's headline is timed with: the fastest in full-solve timings on
+# MI355X (c3's band of 7 strips lies between the autotuner's candidates 4 and 8).
 PINNED = {
     "c1": {"sweep": "diag", "diag_rows": 64, "diag_k": 1, "band": 2, "tile": "0x0"},
     "c2": {"sweep": "diag", "diag_rows": 64, "diag_k": 2, "band": 4, "tile": "0x0"},
