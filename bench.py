@@ -78,11 +78,11 @@ KERNEL_SOURCES = {
               "rom_sweep_f32_8x4.hip", "rom_sweep_f32_8x8.hip", "rom_sweep_f64.hip"],
 }
 MEASURED_TRAFFIC = {  # workload: [(kernel family, shape as in config, source hash, bytes per launch), ...]
-    "c2": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "3a383673ce2258ac", 38870000)],
-    "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "3a383673ce2258ac", 1700000)],
-    "c3": [("strip", {"sweep_tile": "16x16", "band": 7}, "05e4cf45e208737f", 846850000)],
-    "c4": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 4, "waves_per_group": 4}, "3a383673ce2258ac", 471680000)],
-    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "05e4cf45e208737f", 3193120000)],
+    "c2": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "5f792cfb314439d8", 38970000)],
+    "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "5f792cfb314439d8", 1800000)],
+    "c3": [("strip", {"sweep_tile": "16x16", "band": 7}, "5e3f4cc063db399a", 826800000)],
+    "c4": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 4, "waves_per_group": 4}, "5f792cfb314439d8", 460470000)],
+    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "5e3f4cc063db399a", 3177490000)],
 }
 
 

@@ -622,10 +622,12 @@ __global__ __launch_bounds__((64 * diag_max_waves<T, K, PD>())) void diag_kernel
     int& s_ticket = cons[kDiagMaxWaves];
 
     if (!A.mode_all && A.ctl->active == 0) return;   // every system has stopped
-    if (threadIdx.x == 0) atomicMin(&A.ctl->t_first, (unsigned long long)wall_clock64());
     const long long tag = (long long)uniform(A.ctl->epoch) << 24;
     for (;;) {
-        if (threadIdx.x == 0) s_ticket = atomicAdd(&A.ctl->ticket, 1);
+        if (threadIdx.x == 0) {
+            s_ticket = atomicAdd(&A.ctl->ticket, 1);
+            sweep_clock(A.ctl, s_ticket, A.ntickets);
+        }
         if (lane == 0) {
             prod[wave] = 0;
             cons[wave] = 0;
@@ -684,7 +686,6 @@ __global__ __launch_bounds__((64 * diag_max_waves<T, K, PD>())) void diag_kernel
         }
         __syncthreads();  // the band is done before its LDS is reused
     }
-    if (lane == 0) atomicMax(&A.ctl->t_last, (unsigned long long)wall_clock64());
 }
 
 template <typename T, int R, int K, int PD, bool ANG = false>

@@ -199,8 +199,6 @@ void sweep_kernel(SweepArgs A)
     int* consumed = produced + kMaxBand;
     int& s_ticket = consumed[kMaxBand];
     if (!A.mode_all && A.ctl->active == 0) return;  // every system has stopped
-    // sweep duration: first wave start .. last wave end on the device real-time clock
-    if (threadIdx.x == 0) atomicMin(&A.ctl->t_first, (unsigned long long)wall_clock64());
     const int epoch = A.ctl->epoch;
     const long long tag = (long long)epoch << 24;
     const T* __restrict__ sigma_t = (const T*)A.sigma_t;
@@ -211,7 +209,10 @@ void sweep_kernel(SweepArgs A)
     T* __restrict__ edge = (T*)A.edge;
 
     for (;;) {
-        if (threadIdx.x == 0) s_ticket = atomicAdd(&A.ctl->ticket, 1);
+        if (threadIdx.x == 0) {
+            s_ticket = atomicAdd(&A.ctl->ticket, 1);
+            sweep_clock(A.ctl, s_ticket, A.ntickets);
+        }
         if (lane == 0) {
             produced[wave] = 0;
             consumed[wave] = 0;
@@ -556,7 +557,6 @@ void sweep_kernel(SweepArgs A)
         }
         __syncthreads();  // the band is done before its LDS is reused
     }
-    if (threadIdx.x == 0) atomicMax(&A.ctl->t_last, (unsigned long long)wall_clock64());
 }
 
 
