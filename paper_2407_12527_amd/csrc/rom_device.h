@@ -113,13 +113,14 @@ struct Ctl {
     int32_t active;         // systems still running after the last combine step
     int32_t error;          // 1: a dependency wait timed out
     int32_t sweeps;         // sweep launches that did work (timed)
-    int32_t cblocks_done;   // contraction blocks finished (the last one stamps t_mark)
-    int32_t pad;
-    unsigned long long t_first;     // real-time clock at the first wave start of the running sweep
-    unsigned long long t_last;      // ... and at the last wave end
+    int32_t pad0, pad;
+    unsigned long long t_first;     // real-time clock at the running sweep's first ticket claim
+    unsigned long long t_last;      // ... and at its last claim, after all its work
     unsigned long long sweep_ticks; // summed sweep durations (real-time clock ticks)
-    unsigned long long t_mark;      // end of the kernel that precedes the next sweep: a sweep lasts
-                                    // from here (its dispatch, as a profiler sees it) to its last wave
+    unsigned long long t_mark;      // end of the combine step that precedes the next sweep: a sweep
+                                    // lasts from here (its dispatch, as a profiler sees it) to its
+                                    // last claim; a contraction in between clears it (~0), and that
+                                    // sweep is timed from its first claim
 };
 
 }  // namespace rom

@@ -196,7 +196,8 @@ hipError_t launch_init_state(const SystemDev* sys, const ProblemDev* probs, int 
                              hipStream_t s);
 hipError_t launch_moments(const MomentsArgs& a, bool fp64, hipStream_t s);
 hipError_t launch_finish_var(const double* m2, double* var, int64_t cells, int64_t t, hipStream_t s);
-// kind 0 bf16 MFMA, 1 fp32, 2 fp64; ctl (may be NULL): the last block stamps ctl->t_mark
+// kind 0 bf16 MFMA, 1 fp32, 2 fp64; ctl (may be NULL): the kernel clears ctl->t_mark (the next
+// sweep is then timed from its first ticket claim)
 hipError_t launch_contract(const ContractArgs& a, int kind, hipStream_t s, Ctl* ctl = nullptr);
 // Blocks of one contraction (-1: shape not supported by the kind); several contractions in one
 // launch: items [n] on the device, map [nblocks] = (item, block of that item).
