@@ -106,14 +106,20 @@ struct SysCtl {
     double r_prev;
 };
 
+// The three words that many workgroups touch at once sit on cache lines of their own: the ticket
+// counter (claimed by every sweep workgroup), the combine's block counter, and the error flag that
+// long dependency waits poll (c5 step 55.7 -> 55.0 ms against all of them on one line).
 struct Ctl {
     int32_t ticket;         // next strip ticket
-    int32_t epoch;          // sweep generation, tags the progress counters
+    int32_t pad_ticket[31];
     int32_t blocks_done;    // combine blocks finished in this iteration
-    int32_t active;         // systems still running after the last combine step
+    int32_t pad_blocks[31];
     int32_t error;          // 1: a dependency wait timed out
+    int32_t pad_error[31];
+    int32_t epoch;          // sweep generation, tags the progress counters
+    int32_t active;         // systems still running after the last combine step
     int32_t sweeps;         // sweep launches that did work (timed)
-    int32_t pad0, pad;
+    int32_t pad;
     unsigned long long t_first;     // real-time clock at the running sweep's first ticket claim
     unsigned long long t_last;      // ... and at its last claim, after all its work
     unsigned long long sweep_ticks; // summed sweep durations (real-time clock ticks)
