@@ -7,7 +7,7 @@ residual, replayed from captured HIP graphs), FP64 ensemble moments where the wo
 and the results left in HBM.  The default workload is c5, the largest single-GPU configuration: 200
 independent problems (grid sides 64..1024, 16..512 ordinates, random 8 x 8 block maps of cross
 sections) solved together, one persistent sweep launch per iteration.  The sweep shape the headline
-is timed with is pinned per workload (the autotuner's measured pick), so that the timed work does
+is timed with is pinned per workload (the fastest in full-solve timings), so that the timed work does
 not depend on a timing-based choice made in the same process.
 
 The JSON line carries, besides the contract fields:
