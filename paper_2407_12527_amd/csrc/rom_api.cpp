@@ -1154,10 +1154,11 @@ void build_plan(Plan& P, const std::vector<SysInput>& in, const rom_si_opts& o, 
     P.prog_count = std::max(prog_sum, 1);
     take(P, P.d_prog, P.prog_count * sizeof(long long));
     zero(P, P.d_prog.p, P.prog_count * sizeof(long long));
-    take(P, P.d_ctl, sizeof(Ctl));
-    zero(P, P.d_ctl.p, sizeof(Ctl));
-    take(P, P.d_sysctl, P.nsys * sizeof(SysCtl));
-    zero(P, P.d_sysctl.p, P.nsys * sizeof(SysCtl));
+    // the control block and the per-system states in one block (one readback per graph replay)
+    const size_t sc_off = (sizeof(Ctl) + 255) / 256 * 256;
+    take(P, P.d_ctl, sc_off + P.nsys * sizeof(SysCtl));
+    zero(P, P.d_ctl.p, sc_off + P.nsys * sizeof(SysCtl));
+    P.d_sysctl.set_view((char*)P.d_ctl.p + sc_off, P.nsys * sizeof(SysCtl));
     if (max_iter > 0) take(P, P.d_rhist, (size_t)P.nsys * max_iter * sizeof(double));
     if (aniso) {
         take(P, P.d_ang, std::max<int64_t>(ang_sum, 1) * P.esz);
@@ -1466,8 +1467,10 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     auto capture = [&](bool with_initial_state, hipGraph_t& g, hipGraphExec_t& ge) {
         HIPCHK(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
         try {
+            // a later replay's first sweep is timed from a mark at its start, not from the previous
+            // replay's last combine; after the initial state it is timed from its first ticket claim
             if (with_initial_state) enqueue_initial_state();
-            HIPCHK(launch_mark(P.d_ctl.as<Ctl>(), s));  // the sweep is timed from here, not from the combine
+            else HIPCHK(launch_mark(P.d_ctl.as<Ctl>(), s));
             for (int k = 0; k < K; ++k) enqueue_iteration(P, s, tol);
         } catch (...) {
             hipGraph_t gg = nullptr;
@@ -1514,9 +1517,9 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     for (;;) {
         HIPCHK(hipGraphLaunch(launched == 0 ? P.gexec0 : P.gexec, s));
         launched += K;
-        // the control block and the per-system states come back behind one synchronization
-        HIPCHK(hipMemcpyAsync(h_ctl, P.d_ctl.p, sizeof(Ctl), hipMemcpyDeviceToHost, s));
-        HIPCHK(hipMemcpyAsync(h_sc, P.d_sysctl.p, P.nsys * sizeof(SysCtl), hipMemcpyDeviceToHost, s));
+        // the control block and the per-system states (one block, sysctl at sc_off) come back in
+        // one copy behind one synchronization
+        HIPCHK(hipMemcpyAsync(h_ctl, P.d_ctl.p, state_bytes, hipMemcpyDeviceToHost, s));
         HIPCHK(hipEventRecord(e1, s));  // complete once this replay's state is back; the last one ends the timing
         HIPCHK(hipStreamSynchronize(s));
         std::memcpy(&ctl, h_ctl, sizeof(Ctl));

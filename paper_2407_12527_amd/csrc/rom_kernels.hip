@@ -491,7 +491,7 @@ __device__ __forceinline__ void reset_ctl(Ctl* ctl, int nsys)
     ctl->t_first = ~0ull;
     ctl->t_last = 0ull;
     ctl->sweep_ticks = 0ull;
-    ctl->t_mark = wall_clock64();
+    ctl->t_mark = ~0ull;  // the first sweep is timed from its first ticket claim
     ctl->ticket = 0;
     ctl->blocks_done = 0;
     ctl->epoch += 1;
