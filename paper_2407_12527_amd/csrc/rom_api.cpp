@@ -335,6 +335,8 @@ struct Plan {
     DevMem d_ang, d_psi, d_Pt, d_uflags;
     DevMem d_kmsys, d_kmord, d_kmuidx, d_kmdense, d_kminv;  // kernel-matrix build inputs
     DevMem d_citems, d_cmap;  // batched contraction: per-system arguments, (system, block) map
+    DevMem d_moff;            // ensemble moments: flux offsets of the first moff_n systems
+    int moff_n = 0;
     int cmap_blocks = 0;
     std::vector<int64_t> pt_off;  // per system offset into d_Pt (elements)
     hipGraphExec_t gexec = nullptr;   // K iterations
@@ -2368,20 +2370,23 @@ int rom_ensemble(rom_handle* h, int32_t t, uint64_t seed, const rom_ord_spec* sp
     h->res_dev = nullptr;  // the moment buffers and plans are reallocated below
     try {
         hipStream_t s = h->stream();
-        HIPCHK(h->ens_mean.alloc(h->cells * 8));
-        HIPCHK(h->ens_m2.alloc(h->cells * 8));
-        HIPCHK(h->ens_var.alloc(h->cells * 8));
-        std::vector<int64_t> offs;
-        DevMem d_offs;
+        // the moment buffers of the previous call are reused when the size matches (each
+        // reallocation through an allocator hook waits for the device)
+        for (DevMem* d : {&h->ens_mean, &h->ens_m2, &h->ens_var})
+            if (!d->p || d->bytes != (size_t)h->cells * 8) HIPCHK(d->alloc(h->cells * 8));
         EnsAgg ag;
-        // FP64 moments of each batch, merged into the running ones (eq. (4.6))
+        // FP64 moments of each batch, merged into the running ones (eq. (4.6)); the first batch
+        // (done = 0) overwrites them.  The flux offsets live with the plan, uploaded once.
         auto moments = [&](Plan& P, int done, int b) {
-            offs.assign(b, 0);
-            for (int k = 0; k < b; ++k) offs[k] = P.sys[k].phi_off;
-            upload(d_offs, offs);
+            if (P.moff_n != b || !P.d_moff.p) {
+                std::vector<int64_t> offs(b);
+                for (int k = 0; k < b; ++k) offs[k] = P.sys[k].phi_off;
+                upload(P.d_moff, offs);
+                P.moff_n = b;
+            }
             MomentsArgs ma{};
             ma.phi = P.d_phi.p;
-            ma.phi_offs = d_offs.as<int64_t>();
+            ma.phi_offs = P.d_moff.as<int64_t>();
             ma.t = b;
             ma.count = done;
             ma.cells = h->cells;
