@@ -347,6 +347,7 @@ struct Plan {
     // replay (a pageable destination would be staged through a bounce buffer, copy by copy)
     void* h_state = nullptr;
     size_t h_state_bytes = 0;
+    hipEvent_t ev0 = nullptr, ev1 = nullptr;  // device time of a solve (created once per plan)
     int graph_iters = 0;
     int last_iters = 0;   // largest iteration count of the previous solve with this plan
     double graph_tol = 0.0;
@@ -359,6 +360,8 @@ struct Plan {
         if (gexec0) (void)hipGraphExecDestroy(gexec0);
         if (graph0) (void)hipGraphDestroy(graph0);
         if (h_state) (void)hipHostFree(h_state);
+        if (ev0) (void)hipEventDestroy(ev0);
+        if (ev1) (void)hipEventDestroy(ev1);
     }
 
     // the sigma_t and source pools carry kPoolPad elements of padding on both sides
@@ -1442,9 +1445,9 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     }
     if (K == 0) K = P.max_iter <= 64 ? 4 : 8;
     K = std::min(K, P.max_iter);
-    hipEvent_t e0, e1;
-    HIPCHK(hipEventCreate(&e0));
-    HIPCHK(hipEventCreate(&e1));
+    if (!P.ev0) HIPCHK(hipEventCreate(&P.ev0));
+    if (!P.ev1) HIPCHK(hipEventCreate(&P.ev1));
+    hipEvent_t e0 = P.ev0, e1 = P.ev1;
     HIPCHK(hipEventRecord(e0, s));
     // initial state: phi = 0, isotropic source = q (linear kernel: S0 = q, S1 = S2 = 0), angular
     // flux = 0, every system active.  Its arguments are fixed for a plan, so it is captured at the
@@ -1531,8 +1534,6 @@ SolveResult run_si(Plan& P, hipStream_t s, const rom_si_opts& o)
     float ms = 0;
     HIPCHK(hipEventElapsedTime(&ms, e0, e1));
     r.ms = ms;
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
     r.error = ctl.error != 0;
     r.sweep_ms = (double)ctl.sweep_ticks / wallclock_khz();
     r.sweeps = ctl.sweeps;
