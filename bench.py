@@ -78,11 +78,11 @@ KERNEL_SOURCES = {
               "rom_sweep_f32_8x4.hip", "rom_sweep_f32_8x8.hip", "rom_sweep_f64.hip"],
 }
 MEASURED_TRAFFIC = {  # workload: [(kernel family, shape as in config, source hash, bytes per launch), ...]
-    "c2": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "0598a01edc4a0c77", 38850000)],
+    "c2": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 2, "waves_per_group": 4}, "0598a01edc4a0c77", 38940000)],
     "c1": [("row-lane", {"rows_per_block": 64, "ordinates_per_lane": 1, "waves_per_group": 2}, "0598a01edc4a0c77", 1690000)],
-    "c3": [("strip", {"sweep_tile": "16x16", "band": 7}, "1ae15ac46a2bed53", 832430000)],
-    "c4": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 4, "waves_per_group": 4}, "0598a01edc4a0c77", 459470000)],
-    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "1ae15ac46a2bed53", 3175490000)],
+    "c3": [("strip", {"sweep_tile": "16x16", "band": 7}, "1ae15ac46a2bed53", 827140000)],
+    "c4": [("row-lane", {"rows_per_block": 16, "ordinates_per_lane": 4, "waves_per_group": 4}, "0598a01edc4a0c77", 459540000)],
+    "c5": [("strip", {"sweep_tile": "16x16", "band": 4}, "1ae15ac46a2bed53", 3162290000)],
 }
 
 
